@@ -1,0 +1,133 @@
+"""Pins of the oracle's path simulation and caplet pricing (paper Sections 2-3).
+
+* Structural identities of the schemes (Section 3): the last rate is a
+  martingale with drift -kappa(lambda_N) in every scheme, so its caplet is
+  bit-identical in FULL, PICARD and FROZEN; the second-to-last rate's drift
+  depends only on rate N, whose Picard iterate equals the rate itself, so
+  caplet N-1 is bit-identical in FULL and PICARD.
+* Zero volatility: no randomness, drift 0, price delta_i B(0,T_{i+1})(L_i(0) - K)^+.
+* The terminal-measure martingale identity behind eq. (caplet):
+  E[prod_{l>=i}(1 + delta_l L(T_i,T_l))] = prod_{l>=i}(1 + delta_l L(0,T_l)).
+* Brownian special case (c > 0, no jumps): the caplet equals Black's (1976)
+  formula under the caplet's own forward measure.
+* The last rate under the NIG driver: log L_N(T_N)/L_N(0) is a sum of
+  independent scaled NIG increments, so its caplet is a Fourier integral of
+  the characteristic function (Lewis 2001).
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate
+from scipy.stats import norm
+
+import workloads
+
+FULL, PICARD, FROZEN = 0, 1, 2
+
+
+def test_scheme_identities_bit_exact(oracle_mod):
+    for ts in (workloads.plain_fp64(), workloads.gpu_scale(), workloads.kluge_example()):
+        o = oracle_mod.Oracle(ts, seed=1)
+        idx = np.arange(0, 3000, 7)
+        Lf, Df = o.paths(FULL, idx)
+        Lp, Dp = o.paths(PICARD, idx)
+        Lz, Dz = o.paths(FROZEN, idx)
+        N = ts.n_rates
+        assert np.array_equal(Lf[:, N - 1], Lp[:, N - 1])
+        assert np.array_equal(Lf[:, N - 1], Lz[:, N - 1])
+        assert np.array_equal(Df[:, N - 1], Dz[:, N - 1]) and np.all(Df[:, N - 1] == 1.0)
+        assert np.array_equal(Lf[:, N - 2], Lp[:, N - 2])
+        assert np.array_equal(Df[:, N - 2], Dp[:, N - 2])
+        # earlier rates do differ between the schemes
+        assert not np.array_equal(Lf[:, 0], Lp[:, 0])
+        assert not np.array_equal(Lp[:, 0], Lz[:, 0])
+
+
+def test_zero_vol_exact(oracle_mod):
+    ts = workloads.make_structure(7, 0.5, 0.03 + 0.004 * np.arange(7), 4, lambda t, T, r: 0.0,
+                                  [0.7, 1.0, 1.3])
+    o = oracle_mod.Oracle(ts, seed=1)
+    B = ts.B0_T1 / np.cumprod(1.0 + ts.delta * ts.L0)       # B(0, T_{i+1})
+    exact = ts.delta[:, None] * B[:, None] * np.maximum(ts.L0[:, None] - ts.strikes, 0.0)
+    for scheme in (FULL, PICARD, FROZEN):
+        r = o.price(scheme, 100)
+        assert np.allclose(r["price"], exact, rtol=1e-14, atol=1e-18)
+        # one-pass variance E[p^2] - E[p]^2 leaves only FP64 rounding: SE <~ sqrt(eps) p
+        assert np.all(r["stderr"] <= 1e-7 * exact + 1e-18)
+
+
+@pytest.mark.parametrize("wl", ["plain_n10", "stress"])
+def test_martingale_identity_full(oracle_mod, wl):
+    if wl == "stress":
+        ts = workloads.make_structure(8, 0.5, 0.08, 5, lambda t, T, r: 0.3, [1.0],
+                                      alpha=6.0, beta=-1.0, delta_nig=2.0)
+        n = 200000
+    else:
+        ts = workloads.plain_fp64()
+        n = 100000
+    o = oracle_mod.Oracle(ts, seed=3)
+    r = o.price(FULL, n)
+    z = r["mart_resid"] / r["mart_se"]
+    assert np.all(np.abs(z) < 4.0), z
+
+
+def black_caplet(F, K, v, disc, delta):
+    d1 = (math.log(F / K) + 0.5 * v * v) / v
+    d2 = d1 - v
+    return delta * disc * (F * norm.cdf(d1) - K * norm.cdf(d2))
+
+
+def test_brownian_case_matches_black(oracle_mod):
+    ts = workloads.brownian(N=6, delta=0.5, L0=0.05, vol=0.2, c=1.0, steps_per_period=20)
+    o = oracle_mod.Oracle(ts, seed=1)
+    n = 400000
+    r = o.price(FULL, n)
+    B = ts.B0_T1 / np.cumprod(1.0 + ts.delta * ts.L0)       # B(0, T_{i+1})
+    for i in range(ts.n_rates):
+        v = math.sqrt(ts.c * 0.2**2 * ts.tenor[i])
+        for j in range(ts.n_strikes):
+            ref = black_caplet(ts.L0[i], ts.strikes[i, j], v, B[i], ts.delta[i])
+            z = (r["price"][i, j] - ref) / r["stderr"][i, j]
+            assert abs(z) < 4.0, (i, j, r["price"][i, j], ref, z)
+
+
+def _nig_kappa_complex(z, alpha, beta, delta):
+    gamma = math.sqrt(alpha**2 - beta**2)
+    mu = -delta * beta / gamma
+    return mu * z + delta * (gamma - np.sqrt(alpha**2 - (beta + z) ** 2 + 0j))
+
+
+def lewis_terminal_caplet(ts):
+    """E[(L_N(T_N) - K)^+] for the last rate by the Lewis (2001) formula,
+    log(L_N(T_N)/L_N(0)) = sum_k lambda_k dH_k - kappa(lambda_k) dt_k."""
+    N = ts.n_rates
+    s = ts.steps_per_period
+    T = np.concatenate([[0.0], ts.tenor])
+    dts = np.array([(T[k // s + 1] - T[k // s]) / s for k in range(N * s)])
+    lam = ts.vol[:, N - 1]
+    kr = lambda u: _nig_kappa_complex(u, ts.alpha, ts.beta, ts.delta_nig)
+
+    def phi(z):  # E exp(i z X)
+        return np.exp(np.sum(dts * (kr(1j * z * lam) - 1j * z * kr(lam))))
+
+    F = ts.L0[N - 1]
+    out = []
+    for K in ts.strikes[N - 1]:
+        k = math.log(F / K)
+        f = lambda u: (np.exp(1j * u * k) * phi(u - 0.5j)).real / (u * u + 0.25)
+        val, _ = integrate.quad(f, 0.0, np.inf, limit=500, epsabs=1e-14, epsrel=1e-12)
+        out.append(F - math.sqrt(F * K) / math.pi * val)
+    return np.array(out)
+
+
+@pytest.mark.parametrize("wl", ["plain_n10", "gpu_n20", "kluge_n9"])
+def test_terminal_caplet_matches_fourier(oracle_mod, wl):
+    ts = workloads.WORKLOADS[wl]()
+    N = ts.n_rates
+    o = oracle_mod.Oracle(ts, seed=9)
+    n = 200000
+    r = o.price(FROZEN, n)           # caplet N is identical in all schemes
+    ref = ts.delta[N - 1] * o.B0_Tstar() * lewis_terminal_caplet(ts)
+    z = (r["price"][N - 1] - ref) / r["stderr"][N - 1]
+    assert np.all(np.abs(z) < 4.0), (r["price"][N - 1], ref, z)
