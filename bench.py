@@ -1,0 +1,173 @@
+#!/usr/bin/env python3
+"""Throughput of the Lévy LIBOR Monte Carlo path on one MI355X.
+
+One step = one pass of the whole path over the N=20 semiannual workload
+(L0_i = 0.03 + 0.002 i, lambda = 0.12 + 0.1 e^{-0.5 (T_i - t)}, NIG(18, -4, 1),
+20 Euler steps per period, 2^20 paths, strikes {0.8, 1, 1.2} x forward) for
+the full Euler drift and for the Picard drift: FP64 precompute, path kernel
+(FP32 state, FP64 increments and sums) and the fixed-order reduction, each
+scheme on the same stream.  `value` is path-steps per second over both
+schemes (paths x Euler steps x schemes / wall time of the timed steps).
+
+Prints one JSON line.  Only one GPU is used; --gpus above 1 exits.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads  # noqa: E402
+
+PEAK_FP32 = 157.3e12   # MI355X vector FP32, FLOP/s
+Q = 64
+METRIC = "path-steps/s: full Euler vs Picard vs MLP drift, at <=1e-4 rel caplet error"
+
+
+def flops_per_path_step(scheme: str, n: int) -> int:
+    """Algorithmic FP32 flops of one Euler step with n live rates (FMA = 2):
+    suffix recursion 6 per (rate, node) pair over n-1 couplings, plus Q for the
+    top rate, 8 per rate for ell and the update (16 for Picard, which also
+    advances its predictor), 40 for the increment."""
+    if scheme == "full":
+        return 6 * Q * (n - 1) + Q + 8 * n + 40
+    if scheme == "picard":
+        return 6 * Q * (n - 1) + Q + 16 * n + 40
+    if scheme == "frozen":
+        return 4 * n + 40
+    raise ValueError(scheme)
+
+
+def flops_per_path(ts, scheme: str) -> int:
+    s, N = ts.steps_per_period, ts.n_rates
+    return sum(s * flops_per_path_step(scheme, N - m) for m in range(N))
+
+
+def cpu_baseline(ts, n_sample: int, schemes) -> dict:
+    """The FP64 oracle, as it stands, on a bounded sample of the same workload."""
+    import oracle
+    oracle.build(force=False)
+    o = oracle.Oracle(ts, seed=1)
+    total_steps = 0
+    t0 = time.perf_counter()
+    threads = 0
+    for name in schemes:
+        r = o.price_sums({"full": 0, "picard": 1}[name], n_sample)
+        threads = r["threads"]
+        total_steps += n_sample * ts.n_steps
+    dt = time.perf_counter() - t0
+    return {"value": total_steps / dt, "unit": "path-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n_sample} paths x {ts.n_steps} steps x {len(schemes)} schemes "
+                      f"({'+'.join(schemes)}) of the same workload, {dt:.1f} s"}
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--paths", type=int, default=1 << 20)
+    ap.add_argument("--schemes", default="full,picard")
+    ap.add_argument("--cpu-sample", type=int, default=2048,
+                    help="paths of the oracle timing sample (0 skips it)")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
+        return 2
+
+    import torch
+    import paper_1006_3340_amd as lll
+
+    ts = workloads.gpu_scale()
+    schemes = [s for s in args.schemes.split(",") if s]
+    n = args.paths
+    stream = torch.cuda.current_stream()
+    plan = lll.Plan(ts, precision=lll.FP32, max_paths=n)
+    plan.set_timing(True)
+
+    def one_step(record=None):
+        for name in schemes:
+            plan.execute(lll.SCHEMES[name], n, seed=1, stream=stream)
+            if record is not None:
+                t = plan.timing()
+                record.setdefault(name, []).append(t)
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(args.steps):
+        for name in schemes:
+            plan.execute(lll.SCHEMES[name], n, seed=1, stream=stream)
+    end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    elapsed = start.elapsed_time(end) / 1e3
+    # per-stage kernel durations (HIP events recorded by the library on `stream`)
+    rec = {}
+    for _ in range(3):
+        one_step(rec)
+    torch.cuda.synchronize()
+    res = plan.results(stream)
+    if not np.all(np.isfinite(res["price"])):
+        print(json.dumps({"error": "non-finite prices"}))
+        return 1
+
+    path_steps = n * ts.n_steps * len(schemes) * args.steps
+    value = path_steps / elapsed
+    per_scheme = {}
+    for name in schemes:
+        ms = float(np.mean([r["paths"] for r in rec[name]]))
+        fl = flops_per_path(ts, name) * n
+        per_scheme[name] = {
+            "path_kernel_ms": ms,
+            "precompute_ms": float(np.mean([r["precompute"] for r in rec[name]])),
+            "reduce_ms": float(np.mean([r["reduce"] for r in rec[name]])),
+            "path_steps_per_s": n * ts.n_steps / (ms / 1e3),
+            "fp32_tflops": fl / (ms / 1e3) / 1e12,
+            "frac_fp32_peak": fl / (ms / 1e3) / PEAK_FP32,
+        }
+    dom = schemes[0]
+    fl_dom = flops_per_path(ts, dom) * n
+    ms_dom = per_scheme[dom]["path_kernel_ms"]
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "path-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": ts.name, "n_rates": ts.n_rates, "delta": 0.5,
+                   "steps_per_period": ts.steps_per_period, "n_paths": n,
+                   "n_strikes": ts.n_strikes, "driver": "NIG(18,-4,1)", "schemes": schemes},
+        "roofline": {"bound": "alu", "kernel": f"path_kernel<float,24,{dom}>",
+                     "achieved": fl_dom / (ms_dom / 1e3) / 1e12, "peak": PEAK_FP32 / 1e12,
+                     "unit": "TFLOP/s", "frac": fl_dom / (ms_dom / 1e3) / PEAK_FP32,
+                     "traffic": None},
+        "schemes": per_scheme,
+        "wall_s": wall,
+    }
+    if args.cpu_sample > 0:
+        out["cpu_baseline"] = cpu_baseline(ts, args.cpu_sample, schemes)
+    plan.close()
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,180 @@
+/*
+ * lll.h -- C ABI of the MI355X Monte Carlo engine for the Lévy LIBOR model
+ * (Papapantoleon & Skovmand, "Numerical methods for the Lévy LIBOR model").
+ *
+ * One call prices caplets (paper Section 3.3, eq. (caplet)) by simulating
+ * log-LIBOR rates under the terminal measure P_{T_*} (Section 2, eqs.
+ * (LIBOR-dyn-PT), (LIBOR-drift-PT), (log-LIB-SIE)) with an Euler scheme and
+ * one of three drift treatments (Section 3):
+ *
+ *   LLL_FULL    the drift of eq. (LIBOR-drift-PT) at the current rates;
+ *   LLL_PICARD  the drift of eq. (bdrift), evaluated at the second Picard
+ *               iterate Z^(1) of eq. (Picard-2);
+ *   LLL_FROZEN  Z^(1) itself (the drift frozen at the initial rates);
+ *
+ * driven by a normal inverse Gaussian Lévy process (Section 4) or, as a
+ * special case, by a Brownian motion.  The jump integral of the drift is the
+ * closed-form cumulant plus a 64-node quadrature of the coupling term.
+ *
+ * Conventions
+ *   - Rates are 0-indexed: entry r is the paper's rate i = r + 1 with
+ *     maturity T_i; tenor[r] = T_{r+1}; delta[r] = T_{r+2} - T_{r+1}, with
+ *     T_* = tenor[N-1] + delta[N-1].
+ *   - The Euler grid has steps_per_period equal steps in every accrual period
+ *     [T_m, T_{m+1}] (T_0 = 0); step k lies in period m = k / steps_per_period.
+ *   - vol is lambda(t_k, T_{r+1}) at the left point of step k, row-major
+ *     [N * steps_per_period][N]; entries of rates already fixed are ignored.
+ *   - strikes are absolute, row-major [N][n_strikes].
+ *   - Random numbers: one Philox-4x32-10 call per (step k, path p) with
+ *     counter (k, p mod 2^32, p div 2^32, struct_id | tag << 24) and key
+ *     (seed mod 2^32, seed div 2^32); tag 0 is used for pricing.
+ *   - All pointers named *_host are caller-owned host memory, read or written
+ *     during the call only; pointers named *_dev are device memory of the
+ *     current HIP device.  `stream` is a hipStream_t (NULL = default stream).
+ *
+ * Errors: every function returns LLL_OK (0) or a negative lll_status and
+ * never throws or aborts; lll_last_error() gives a thread-local message for
+ * the last failing call on the calling thread.  Validation of the inputs
+ * happens on the host before any device work.
+ */
+#ifndef LLL_H
+#define LLL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LLL_N_MAX 40        /* largest number of rates N */
+#define LLL_N_MAX_FP64 24   /* largest N for the FP64 path kernel */
+#define LLL_S_MAX 8         /* largest number of strikes per caplet */
+#define LLL_Q 64            /* quadrature nodes of the coupling integral */
+#define LLL_NSTAT(S) (3 * (S) + 2) /* path statistics per caplet */
+
+typedef enum {
+    LLL_OK = 0,
+    LLL_EINVAL = -1,       /* malformed input: sizes, ordering, signs, NaN */
+    LLL_EMOMENT = -2,      /* exponential-moment condition fails: drift integral diverges */
+    LLL_ENOMEM = -3,       /* device allocation failed */
+    LLL_EHIP = -4,         /* a HIP runtime call failed (message has the HIP error) */
+    LLL_EUNSUPPORTED = -5, /* valid input outside what this build handles */
+    LLL_ENUMERIC = -6      /* non-finite payoffs were produced */
+} lll_status;
+
+typedef enum { LLL_FULL = 0, LLL_PICARD = 1, LLL_FROZEN = 2 } lll_scheme;
+typedef enum { LLL_DRIVER_NIG = 0, LLL_DRIVER_BROWNIAN = 1 } lll_driver;
+typedef enum { LLL_FP32 = 0, LLL_FP64 = 1 } lll_precision;
+
+/* One term structure, its driver and its caplet strikes (host memory).
+ * Paper Section 2: tenor 0 = T_0 < T_1 < ... < T_N < T_* (delta_i = T_{i+1} - T_i),
+ * L(0, T_i) > 0 (assumption (LR2)), bounded deterministic vols lambda(., T_i)
+ * (assumption (LR1)).  NIG driver: alpha > |beta|, delta_nig > 0, its drift
+ * chosen so that H is a martingale; Brownian driver: c >= 0. */
+typedef struct {
+    int32_t n_rates;            /* N, 1..LLL_N_MAX */
+    int32_t steps_per_period;   /* s >= 1 */
+    int32_t n_strikes;          /* S, 1..LLL_S_MAX */
+    int32_t driver;             /* lll_driver */
+    uint32_t struct_id;         /* fourth Philox counter word (low 24 bits) */
+    int32_t reserved;
+    const double *tenor;        /* [N] T_1..T_N, strictly increasing, > 0 */
+    const double *delta;        /* [N] accrual fractions, > 0, matching tenor gaps */
+    const double *L0;           /* [N] L(0, T_i) > 0 */
+    double B0_T1;               /* B(0, T_1); <= 0 means 1 / (1 + T_1 L(0, T_1)) */
+    const double *vol;          /* [N*s][N] lambda(t_k, T_i) */
+    const double *strikes;      /* [N][S] */
+    double alpha, beta, delta_nig; /* NIG parameters */
+    double c;                   /* Brownian variance rate */
+} lll_term_structure;
+
+/* Opaque plan: validated inputs copied to the device, precompute tables and
+ * reduction buffers for up to max_paths paths.  Owned by the library. */
+typedef struct lll_plan lll_plan;
+
+const char *lll_version(void);
+const char *lll_last_error(void);
+
+/* Validate `ts` (host) and allocate a plan on the current device for at most
+ * `max_paths` paths per execute call, computing in `precision` (lll_precision:
+ * FP32 path arithmetic with FP64 increments and sums, or FP64 throughout).
+ * The inputs are copied; `ts` may be freed after return.  Synchronous. */
+int lll_plan_create(const lll_term_structure *ts, int precision, int64_t max_paths,
+                    lll_plan **plan_out);
+
+/* Enqueue one pricing pass on `stream`: FP64 precompute of the quadrature rule
+ * and of the cumulant, quadrature and frozen-drift tables; the path kernel over
+ * paths path_offset .. path_offset + n_paths - 1; the deterministic FP64
+ * reduction of the payoff sums.  Asynchronous: results are read with
+ * lll_plan_results.  If path_fix_dev is not NULL it receives, for every path
+ * j of this call and caplet r, L(T_r, T_r) at [j][2r] and the terminal-measure
+ * factor prod_{l>r}(1 + delta_l L(T_r, T_l)) at [j][2r+1] (FP64, n_paths x 2N). */
+int lll_plan_execute(lll_plan *plan, int scheme, int64_t n_paths, int64_t path_offset,
+                     uint64_t seed, double *path_fix_dev, void *stream);
+
+/* Wait for `stream` and copy the results of the last execute to the host.
+ * price_host, stderr_host, n_itm_host: [N][S]; mart_resid_host, mart_se_host: [N]
+ * (mean of prod_{l>=i}(1 + delta_l L(T_i, T_l)) minus its time-0 value, and its
+ * standard error).  Any output pointer may be NULL.  Returns LLL_ENUMERIC if a
+ * price or standard error is not finite. */
+int lll_plan_results(lll_plan *plan, double *price_host, double *stderr_host,
+                     double *mart_resid_host, double *mart_se_host, double *n_itm_host,
+                     void *stream);
+
+/* Raw per-caplet sums of the last execute, [N][LLL_NSTAT(S)] doubles:
+ * sum p_j (S), sum p_j^2 (S), in-the-money counts (S), sum M, sum M^2 with
+ * p_j = prod_{l>i}(1 + delta L)(L_i - K_j)^+ and M = prod_{l>=i}(1 + delta L). */
+int lll_plan_sums(lll_plan *plan, double *sums_host, void *stream);
+
+/* Per-wavefront partial sums of the last execute ([n_waves][N][NSTAT], FP64),
+ * the input of the fixed-order reduction.  n_waves = ceil(n_paths / 64). */
+int lll_plan_partials(lll_plan *plan, double *partials_host, int64_t capacity, void *stream);
+
+/* Record HIP events around the three stages of every later execute on its
+ * stream (enable != 0) or stop recording (enable == 0). */
+int lll_plan_set_timing(lll_plan *plan, int enable);
+
+/* Durations in milliseconds of the last timed execute: ms_host[0] precompute,
+ * ms_host[1] path kernel, ms_host[2] reduction.  Waits for the last event. */
+int lll_plan_timing(lll_plan *plan, float *ms_host);
+
+int lll_plan_destroy(lll_plan *plan);
+
+/* One-shot convenience: create a plan, execute on `stream`, read the results,
+ * destroy.  Outputs as in lll_plan_results (any may be NULL). */
+int lll_price_caplets(const lll_term_structure *ts, int64_t n_paths, int scheme, uint64_t seed,
+                      int precision, double *price_host, double *stderr_host,
+                      double *mart_resid_host, void *stream);
+
+/* ---- inspection entry points (used by the parity tests) ---- */
+
+/* Philox-4x32-10 words computed on the device for n counters ctr_host[n][4]
+ * and keys key_host[n][2]; out_host[n][4]. */
+int lll_philox(const uint32_t *ctr_host, const uint32_t *key_host, int64_t n,
+               uint32_t *out_host, void *stream);
+
+/* Driver increments of step k for paths p0 .. p0 + n - 1 as drawn by the path
+ * kernel (FP64): subordinator draws V_host[n] (0 for the Brownian driver) and
+ * increments dH_host[n].  Runs the plan's precompute first. */
+int lll_plan_increments(lll_plan *plan, int k, int64_t p0, int64_t n, uint64_t seed,
+                        double *V_host, double *dH_host, void *stream);
+
+/* FP64 precompute tables of the plan (after lll_plan_execute or
+ * lll_plan_increments): nodes x_host[Q], weights w_host[Q] (Lévy density
+ * included), kappa_host[K][N] = kappa(lambda_{k,i}), E_host[K][N][Q] =
+ * e^{lambda_{k,i} x_q} - 1, b0_host[K][N] = drift at the initial rates; entries
+ * of fixed rates are 0.  K = N * steps_per_period.  Any pointer may be NULL. */
+int lll_plan_tables(lll_plan *plan, double *x_host, double *w_host, double *kappa_host,
+                    double *E_host, double *b0_host, void *stream);
+
+/* Drift b(t_k, T_i) of the live rates at step k for n given rate vectors
+ * L_host[n][N], computed by the path kernel's own drift code in the plan's
+ * precision; b_host[n][N] (entries of fixed rates are 0). */
+int lll_plan_drift(lll_plan *plan, int k, const double *L_host, int64_t n, double *b_host,
+                   void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LLL_H */

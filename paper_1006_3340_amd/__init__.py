@@ -1,0 +1,11 @@
+"""MI355X Monte Carlo engine for the Lévy LIBOR model (Papapantoleon & Skovmand).
+
+The computation lives in the HIP library ``liblll.so`` behind the C ABI of
+``include/lll.h``; this package is its thin Python binding.  Importing the
+package does not load the library; the first call does, and raises if the
+library is missing.
+"""
+from ._lib import (FP32, FP64, FROZEN, FULL, PICARD, LLLError, Plan, load, philox,  # noqa: F401
+                   price_caplets, version)
+
+SCHEMES = {"full": FULL, "picard": PICARD, "frozen": FROZEN}

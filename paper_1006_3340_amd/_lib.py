@@ -1,0 +1,259 @@
+"""ctypes binding of the C ABI in include/lll.h (argument marshalling only).
+
+Every step of the computation runs in the HIP library ``liblll.so``; this
+module converts numpy inputs to the ABI's plain pointers and sizes, turns
+status codes into exceptions and returns numpy outputs.  There is no
+fallback: if the library is missing or fails to load, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblll.so")
+
+LLL_OK = 0
+STATUS = {0: "LLL_OK", -1: "LLL_EINVAL", -2: "LLL_EMOMENT", -3: "LLL_ENOMEM", -4: "LLL_EHIP",
+          -5: "LLL_EUNSUPPORTED", -6: "LLL_ENUMERIC"}
+FULL, PICARD, FROZEN = 0, 1, 2
+FP32, FP64 = 0, 1
+N_MAX, N_MAX_FP64, S_MAX, Q = 40, 24, 8, 64
+
+EXPORTS = ["lll_version", "lll_last_error", "lll_plan_create", "lll_plan_execute",
+           "lll_plan_results", "lll_plan_sums", "lll_plan_partials", "lll_plan_destroy",
+           "lll_price_caplets", "lll_philox", "lll_plan_increments", "lll_plan_tables",
+           "lll_plan_drift", "lll_plan_set_timing", "lll_plan_timing"]
+
+
+class LLLError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"{STATUS.get(code, code)}: {message}")
+        self.code = code
+
+
+class TermStructureC(ctypes.Structure):
+    _fields_ = [
+        ("n_rates", ctypes.c_int32),
+        ("steps_per_period", ctypes.c_int32),
+        ("n_strikes", ctypes.c_int32),
+        ("driver", ctypes.c_int32),
+        ("struct_id", ctypes.c_uint32),
+        ("reserved", ctypes.c_int32),
+        ("tenor", ctypes.POINTER(ctypes.c_double)),
+        ("delta", ctypes.POINTER(ctypes.c_double)),
+        ("L0", ctypes.POINTER(ctypes.c_double)),
+        ("B0_T1", ctypes.c_double),
+        ("vol", ctypes.POINTER(ctypes.c_double)),
+        ("strikes", ctypes.POINTER(ctypes.c_double)),
+        ("alpha", ctypes.c_double),
+        ("beta", ctypes.c_double),
+        ("delta_nig", ctypes.c_double),
+        ("c", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def load():
+    """Load liblll.so (built by ``__graft_entry__.build()``); raise if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library {LIB_PATH} is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64, u64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_int
+    dp = ctypes.POINTER(ctypes.c_double)
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    lib.lll_version.restype = ctypes.c_char_p
+    lib.lll_last_error.restype = ctypes.c_char_p
+    lib.lll_plan_create.argtypes = [ctypes.POINTER(TermStructureC), i32, i64, ctypes.POINTER(vp)]
+    lib.lll_plan_execute.argtypes = [vp, i32, i64, i64, u64, vp, vp]
+    lib.lll_plan_results.argtypes = [vp, dp, dp, dp, dp, dp, vp]
+    lib.lll_plan_sums.argtypes = [vp, dp, vp]
+    lib.lll_plan_partials.argtypes = [vp, dp, i64, vp]
+    lib.lll_plan_destroy.argtypes = [vp]
+    lib.lll_price_caplets.argtypes = [ctypes.POINTER(TermStructureC), i64, i32, u64, i32, dp, dp,
+                                      dp, vp]
+    lib.lll_philox.argtypes = [u32p, u32p, i64, u32p, vp]
+    lib.lll_plan_increments.argtypes = [vp, i32, i64, i64, u64, dp, dp, vp]
+    lib.lll_plan_tables.argtypes = [vp, dp, dp, dp, dp, dp, vp]
+    lib.lll_plan_drift.argtypes = [vp, i32, dp, i64, dp, vp]
+    lib.lll_plan_set_timing.argtypes = [vp, i32]
+    lib.lll_plan_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_float)]
+    for name in EXPORTS:
+        if name not in ("lll_version", "lll_last_error"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != LLL_OK:
+        msg = load().lll_last_error().decode(errors="replace")
+        raise LLLError(rc, msg)
+
+
+def _dp(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def stream_handle(stream) -> Optional[int]:
+    """hipStream_t of a torch stream (or an int handle); None = default stream."""
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+def device_ptr(t) -> Optional[int]:
+    """Device address of a torch tensor (or an int address); None passes NULL."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return int(t.data_ptr())
+
+
+class _TS:
+    """Keeps the numpy arrays behind one lll_term_structure alive."""
+
+    def __init__(self, ts):
+        ts.validate_shapes()
+        f64 = lambda a: np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+        self.arrays = [f64(ts.tenor), f64(ts.delta), f64(ts.L0), f64(ts.vol), f64(ts.strikes)]
+        c = TermStructureC()
+        c.n_rates = ts.n_rates
+        c.steps_per_period = ts.steps_per_period
+        c.n_strikes = ts.n_strikes
+        c.driver = int(ts.driver)
+        c.struct_id = int(ts.struct_id) & 0xFFFFFFFF
+        c.tenor, c.delta, c.L0, c.vol, c.strikes = [_dp(a) for a in self.arrays]
+        c.B0_T1 = float(ts.B0_T1)
+        c.alpha, c.beta, c.delta_nig, c.c = (float(ts.alpha), float(ts.beta),
+                                             float(ts.delta_nig), float(ts.c))
+        self.c = c
+
+
+class Plan:
+    """lll_plan: one term structure resident on the current HIP device."""
+
+    def __init__(self, ts, precision: int = FP32, max_paths: int = 1 << 20):
+        self.lib = load()
+        self._ts = _TS(ts)
+        self.N, self.S = ts.n_rates, ts.n_strikes
+        self.K = ts.n_rates * ts.steps_per_period
+        self.max_paths = int(max_paths)
+        h = ctypes.c_void_p()
+        _check(self.lib.lll_plan_create(ctypes.byref(self._ts.c), int(precision),
+                                        int(max_paths), ctypes.byref(h)))
+        self.h = h
+        self.n_paths = 0
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.lll_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def execute(self, scheme: int, n_paths: int, seed: int = 1, path_offset: int = 0,
+                path_fix=None, stream=None):
+        _check(self.lib.lll_plan_execute(self.h, int(scheme), int(n_paths), int(path_offset),
+                                         int(seed), device_ptr(path_fix), stream_handle(stream)))
+        self.n_paths = int(n_paths)
+
+    def set_timing(self, enable: bool = True):
+        _check(self.lib.lll_plan_set_timing(self.h, 1 if enable else 0))
+
+    def timing(self) -> dict:
+        """Durations (ms) of the last timed execute's stages, from HIP events."""
+        ms = (ctypes.c_float * 3)()
+        _check(self.lib.lll_plan_timing(self.h, ms))
+        return {"precompute": ms[0], "paths": ms[1], "reduce": ms[2]}
+
+    def results(self, stream=None) -> dict:
+        N, S = self.N, self.S
+        price = np.zeros((N, S)); se = np.zeros((N, S)); itm = np.zeros((N, S))
+        mart = np.zeros(N); mse = np.zeros(N)
+        _check(self.lib.lll_plan_results(self.h, _dp(price), _dp(se), _dp(mart), _dp(mse),
+                                         _dp(itm), stream_handle(stream)))
+        return {"price": price, "stderr": se, "mart_resid": mart, "mart_se": mse,
+                "n_itm": itm, "n_paths": self.n_paths}
+
+    def sums(self, stream=None) -> np.ndarray:
+        out = np.zeros((self.N, 3 * self.S + 2))
+        _check(self.lib.lll_plan_sums(self.h, _dp(out), stream_handle(stream)))
+        return out
+
+    def partials(self, stream=None) -> np.ndarray:
+        waves = (self.n_paths + 63) // 64
+        out = np.zeros((waves, self.N, 3 * self.S + 2))
+        _check(self.lib.lll_plan_partials(self.h, _dp(out), out.size, stream_handle(stream)))
+        return out
+
+    def increments(self, k: int, p0: int, n: int, seed: int = 1, stream=None):
+        V = np.zeros(n); dH = np.zeros(n)
+        _check(self.lib.lll_plan_increments(self.h, int(k), int(p0), int(n), int(seed), _dp(V),
+                                            _dp(dH), stream_handle(stream)))
+        return V, dH
+
+    def tables(self, stream=None) -> dict:
+        K, N = self.K, self.N
+        x = np.zeros(Q); w = np.zeros(Q); kap = np.zeros((K, N)); E = np.zeros((K, N, Q))
+        b0 = np.zeros((K, N))
+        _check(self.lib.lll_plan_tables(self.h, _dp(x), _dp(w), _dp(kap), _dp(E), _dp(b0),
+                                        stream_handle(stream)))
+        return {"x": x, "w": w, "kappa": kap, "E": E, "b0": b0}
+
+    def drift(self, k: int, L: np.ndarray, stream=None) -> np.ndarray:
+        L = np.ascontiguousarray(np.atleast_2d(np.asarray(L, dtype=np.float64)))
+        b = np.zeros_like(L)
+        _check(self.lib.lll_plan_drift(self.h, int(k), _dp(L), L.shape[0], _dp(b),
+                                       stream_handle(stream)))
+        return b
+
+
+def price_caplets(ts, n_paths: int, scheme: int = FULL, seed: int = 1, precision: int = FP32,
+                  stream=None) -> dict:
+    """lll_price_caplets: prices, standard errors and martingale residuals."""
+    lib = load()
+    t = _TS(ts)
+    N, S = ts.n_rates, ts.n_strikes
+    price = np.zeros((N, S)); se = np.zeros((N, S)); mart = np.zeros(N)
+    _check(lib.lll_price_caplets(ctypes.byref(t.c), int(n_paths), int(scheme), int(seed),
+                                 int(precision), _dp(price), _dp(se), _dp(mart),
+                                 stream_handle(stream)))
+    return {"price": price, "stderr": se, "mart_resid": mart}
+
+
+def philox(ctr: np.ndarray, key: np.ndarray, stream=None) -> np.ndarray:
+    """lll_philox: Philox-4x32-10 words computed on the device."""
+    lib = load()
+    ctr = np.ascontiguousarray(np.asarray(ctr, dtype=np.uint32).reshape(-1, 4))
+    key = np.ascontiguousarray(np.asarray(key, dtype=np.uint32).reshape(-1, 2))
+    n = ctr.shape[0]
+    out = np.zeros((n, 4), dtype=np.uint32)
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    _check(lib.lll_philox(ctr.ctypes.data_as(u32p), key.ctypes.data_as(u32p), n,
+                          out.ctypes.data_as(u32p), stream_handle(stream)))
+    return out
+
+
+def version() -> str:
+    return load().lll_version().decode()

@@ -1,0 +1,425 @@
+// abi.hip -- the extern "C" boundary: validation, plan lifetime, launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lll.h"
+#include "lll_internal.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(LLL_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool finite_all(const double *a, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(a[i])) return false;
+    return true;
+}
+
+// Input checks of paper Section 2: (LR2) positive forwards and a strictly
+// increasing tenor with matching accrual fractions; (LR1) bounded vols with
+// exponential moments -- for the NIG driver the drift integral is finite iff
+// the live vols satisfy Lambda_+ < alpha - beta and Lambda_- < alpha + beta.
+int validate(const lll_term_structure *ts) {
+    if (!ts) return fail(LLL_EINVAL, "term structure is NULL");
+    const int N = ts->n_rates, s = ts->steps_per_period, S = ts->n_strikes;
+    if (N < 1 || N > LLL_N_MAX) return fail(LLL_EINVAL, "n_rates=%d outside 1..%d", N, LLL_N_MAX);
+    if (s < 1 || s > 100000) return fail(LLL_EINVAL, "steps_per_period=%d must be >= 1", s);
+    if ((int64_t)N * s > (int64_t)1 << 24) return fail(LLL_EINVAL, "too many Euler steps");
+    if (S < 1 || S > LLL_S_MAX) return fail(LLL_EINVAL, "n_strikes=%d outside 1..%d", S, LLL_S_MAX);
+    if (!ts->tenor || !ts->delta || !ts->L0 || !ts->vol || !ts->strikes)
+        return fail(LLL_EINVAL, "NULL input array");
+    if (ts->driver != LLL_DRIVER_NIG && ts->driver != LLL_DRIVER_BROWNIAN)
+        return fail(LLL_EINVAL, "unknown driver %d", ts->driver);
+    if (!finite_all(ts->tenor, N) || !finite_all(ts->delta, N) || !finite_all(ts->L0, N) ||
+        !finite_all(ts->vol, (size_t)N * s * N) || !finite_all(ts->strikes, (size_t)N * S) ||
+        !std::isfinite(ts->B0_T1))
+        return fail(LLL_EINVAL, "non-finite input value");
+    double prev = 0.0;
+    for (int r = 0; r < N; ++r) {
+        if (!(ts->tenor[r] > prev)) return fail(LLL_EINVAL, "tenor not strictly increasing at %d", r);
+        if (!(ts->delta[r] > 0.0)) return fail(LLL_EINVAL, "delta[%d] <= 0", r);
+        if (!(ts->L0[r] > 0.0)) return fail(LLL_EINVAL, "L0[%d] <= 0", r);
+        prev = ts->tenor[r];
+    }
+    for (int r = 0; r + 1 < N; ++r) {
+        const double gap = ts->tenor[r + 1] - ts->tenor[r];
+        if (std::fabs(gap - ts->delta[r]) > 1e-9 * std::fmax(1.0, gap))
+            return fail(LLL_EINVAL, "delta[%d]=%g does not match tenor gap %g", r, ts->delta[r], gap);
+    }
+    if (ts->B0_T1 > 1.0) return fail(LLL_EINVAL, "B0_T1=%g > 1", ts->B0_T1);
+    if (ts->driver == LLL_DRIVER_NIG) {
+        if (!(ts->alpha > std::fabs(ts->beta)) || !std::isfinite(ts->alpha))
+            return fail(LLL_EINVAL, "NIG needs alpha > |beta| (alpha=%g beta=%g)", ts->alpha, ts->beta);
+        if (!(ts->delta_nig > 0.0) || !std::isfinite(ts->delta_nig))
+            return fail(LLL_EINVAL, "NIG delta must be > 0");
+        double lp = 0.0, lm = 0.0;
+        for (int k = 0; k < N * s; ++k) {
+            double sp = 0.0, sm = 0.0;
+            for (int r = k / s; r < N; ++r) {
+                const double v = ts->vol[(size_t)k * N + r];
+                sp += std::fmax(v, 0.0);
+                sm += std::fmax(-v, 0.0);
+            }
+            lp = std::fmax(lp, sp);
+            lm = std::fmax(lm, sm);
+        }
+        if (!(lp < ts->alpha - ts->beta) || !(lm < ts->alpha + ts->beta))
+            return fail(LLL_EMOMENT,
+                        "exponential moments fail: Lambda+=%g vs alpha-beta=%g, Lambda-=%g vs "
+                        "alpha+beta=%g",
+                        lp, ts->alpha - ts->beta, lm, ts->alpha + ts->beta);
+    } else {
+        if (!(ts->c >= 0.0) || !std::isfinite(ts->c)) return fail(LLL_EINVAL, "Brownian c < 0");
+    }
+    return LLL_OK;
+}
+
+template <typename T>
+hipError_t dalloc(T **p, size_t n) {
+    return hipMalloc(reinterpret_cast<void **>(p), n * sizeof(T) + 16);
+}
+
+void free_tables(lll::DeviceTables &d) {
+    void *ptrs[] = {d.tenor, d.delta, d.L0, d.vol, d.strikes, d.x, d.w, d.kappa, d.E, d.b0,
+                    d.steps, d.lam_pm, d.ew, d.lam, d.drift0, d.frozen, d.dt, d.cinv, d.L0s,
+                    d.deltas, d.partials, d.chunks, d.sums, d.results};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    d = lll::DeviceTables{};
+}
+
+hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+}  // namespace
+
+extern "C" {
+
+const char *lll_version(void) { return "lll-mi355x 0.1 (gfx950)"; }
+
+const char *lll_last_error(void) { return g_last_error.c_str(); }
+
+int lll_plan_create(const lll_term_structure *ts, int precision, int64_t max_paths,
+                    lll_plan **plan_out) {
+    if (!plan_out) return fail(LLL_EINVAL, "plan_out is NULL");
+    *plan_out = nullptr;
+    int rc = validate(ts);
+    if (rc != LLL_OK) return rc;
+    if (precision != LLL_FP32 && precision != LLL_FP64)
+        return fail(LLL_EINVAL, "unknown precision %d", precision);
+    if (max_paths < 1 || max_paths > ((int64_t)1 << 36))
+        return fail(LLL_EINVAL, "max_paths=%lld outside 1..2^36", (long long)max_paths);
+    if (precision == LLL_FP64 && ts->n_rates > LLL_N_MAX_FP64)
+        return fail(LLL_EUNSUPPORTED, "FP64 path kernel handles N <= %d", LLL_N_MAX_FP64);
+
+    lll_plan *p = new (std::nothrow) lll_plan();
+    if (!p) return fail(LLL_ENOMEM, "host allocation failed");
+    p->N = ts->n_rates;
+    p->s = ts->steps_per_period;
+    p->S = ts->n_strikes;
+    p->K = p->N * p->s;
+    p->driver = ts->driver;
+    p->precision = precision;
+    p->nmax = lll::bucket_for(p->N);
+    p->off = p->nmax - p->N;
+    p->struct_id = ts->struct_id;
+    p->B0_T1 = ts->B0_T1 > 0.0 ? ts->B0_T1 : 1.0 / (1.0 + ts->tenor[0] * ts->L0[0]);
+    p->alpha = ts->alpha;
+    p->beta = ts->beta;
+    p->delta_nig = ts->delta_nig;
+    p->c = ts->c;
+    p->max_paths = max_paths;
+    p->max_waves = (max_paths + lll::kWaveSize - 1) / lll::kWaveSize;
+    p->max_chunks = (p->max_waves + 255) / 256;
+    p->tenor.assign(ts->tenor, ts->tenor + p->N);
+    p->delta.assign(ts->delta, ts->delta + p->N);
+    p->L0.assign(ts->L0, ts->L0 + p->N);
+    p->vol.assign(ts->vol, ts->vol + (size_t)p->K * p->N);
+    p->strikes.assign(ts->strikes, ts->strikes + (size_t)p->N * p->S);
+    (void)hipGetDevice(&p->device);
+
+    const size_t esz = precision == LLL_FP64 ? sizeof(double) : sizeof(float);
+    const size_t N = p->N, K = p->K, NM = p->nmax, S = p->S;
+    const size_t nstat = 3 * S + 2;
+    lll::DeviceTables &d = p->d;
+    hipError_t e = hipSuccess;
+    auto A = [&](auto **ptr, size_t n) {
+        if (e == hipSuccess) e = dalloc(ptr, n);
+    };
+    A(&d.tenor, N); A(&d.delta, N); A(&d.L0, N); A(&d.vol, K * N); A(&d.strikes, N * S);
+    A(&d.x, lll::kQSize); A(&d.w, lll::kQSize); A(&d.kappa, K * N); A(&d.E, K * N * lll::kQSize);
+    A(&d.b0, K * N); A(&d.steps, 4 * N); A(&d.lam_pm, 2);
+    auto AB = [&](void **ptr, size_t n) {
+        if (e == hipSuccess) e = hipMalloc(ptr, n * esz + 16);
+    };
+    AB(&d.ew, K * lll::kQSize * NM * 2); AB(&d.lam, K * NM); AB(&d.drift0, K * NM);
+    AB(&d.frozen, K * NM); AB(&d.dt, K); AB(&d.cinv, NM);
+    A(&d.L0s, NM); A(&d.deltas, NM);
+    A(&d.partials, (size_t)p->max_waves * N * nstat);
+    A(&d.chunks, (size_t)p->max_chunks * N * nstat);
+    A(&d.sums, N * nstat);
+    A(&d.results, 3 * N * S + 2 * N);
+    if (e != hipSuccess) {
+        free_tables(d);
+        delete p;
+        return fail(e == hipErrorOutOfMemory ? LLL_ENOMEM : LLL_EHIP, "device allocation: %s",
+                    hipGetErrorString(e));
+    }
+    auto H2D = [&](double *dst, const std::vector<double> &src) {
+        if (e == hipSuccess) e = hipMemcpy(dst, src.data(), src.size() * sizeof(double),
+                                           hipMemcpyHostToDevice);
+    };
+    H2D(d.tenor, p->tenor); H2D(d.delta, p->delta); H2D(d.L0, p->L0); H2D(d.vol, p->vol);
+    H2D(d.strikes, p->strikes);
+    if (e != hipSuccess) {
+        free_tables(d);
+        delete p;
+        return hip_fail(e, "copying inputs to the device");
+    }
+    *plan_out = p;
+    return LLL_OK;
+}
+
+int lll_plan_set_timing(lll_plan *plan, int enable) {
+    if (!plan) return fail(LLL_EINVAL, "plan is NULL");
+    if (enable && !plan->ev[0]) {
+        for (int i = 0; i < 4; ++i) {
+            hipError_t e = hipEventCreate(&plan->ev[i]);
+            if (e != hipSuccess) return hip_fail(e, "creating timing events");
+        }
+    }
+    plan->timing = enable != 0;
+    plan->timed = false;
+    return LLL_OK;
+}
+
+int lll_plan_timing(lll_plan *plan, float *ms_host) {
+    if (!plan || !ms_host) return fail(LLL_EINVAL, "NULL argument");
+    if (!plan->timed) return fail(LLL_EINVAL, "no timed execute recorded");
+    hipError_t e = hipEventSynchronize(plan->ev[3]);
+    for (int i = 0; i < 3 && e == hipSuccess; ++i)
+        e = hipEventElapsedTime(&ms_host[i], plan->ev[i], plan->ev[i + 1]);
+    if (e != hipSuccess) return hip_fail(e, "reading timing events");
+    return LLL_OK;
+}
+
+int lll_plan_destroy(lll_plan *plan) {
+    if (!plan) return LLL_OK;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    if (dev != plan->device) (void)hipSetDevice(plan->device);
+    for (int i = 0; i < 4; ++i)
+        if (plan->ev[i]) (void)hipEventDestroy(plan->ev[i]);
+    free_tables(plan->d);
+    if (dev != plan->device) (void)hipSetDevice(dev);
+    delete plan;
+    return LLL_OK;
+}
+
+int lll_plan_execute(lll_plan *plan, int scheme, int64_t n_paths, int64_t path_offset,
+                     uint64_t seed, double *path_fix_dev, void *stream) {
+    if (!plan) return fail(LLL_EINVAL, "plan is NULL");
+    if (scheme != LLL_FULL && scheme != LLL_PICARD && scheme != LLL_FROZEN)
+        return fail(LLL_EINVAL, "unknown scheme %d", scheme);
+    if (n_paths < 1 || n_paths > plan->max_paths)
+        return fail(LLL_EINVAL, "n_paths=%lld outside 1..%lld", (long long)n_paths,
+                    (long long)plan->max_paths);
+    if (path_offset < 0 || path_offset > ((int64_t)1 << 62))
+        return fail(LLL_EINVAL, "path_offset=%lld out of range", (long long)path_offset);
+    hipStream_t st = as_stream(stream);
+    const bool t = plan->timing;
+    hipError_t e = t ? hipEventRecord(plan->ev[0], st) : hipSuccess;
+    if (e == hipSuccess) e = lll::launch_precompute(*plan, st);
+    if (e != hipSuccess) return hip_fail(e, "precompute launch");
+    if (t) e = hipEventRecord(plan->ev[1], st);
+    if (e == hipSuccess) e = lll::launch_paths(*plan, scheme, n_paths, path_offset, seed,
+                                              path_fix_dev, st);
+    if (e != hipSuccess) return hip_fail(e, "path kernel launch");
+    if (t) e = hipEventRecord(plan->ev[2], st);
+    if (e == hipSuccess) e = lll::launch_reduce(*plan, n_paths, st);
+    if (e != hipSuccess) return hip_fail(e, "reduction launch");
+    if (t) e = hipEventRecord(plan->ev[3], st);
+    if (e != hipSuccess) return hip_fail(e, "recording timing event");
+    plan->timed = t;
+    plan->last_n_paths = n_paths;
+    plan->executed = true;
+    return LLL_OK;
+}
+
+int lll_plan_results(lll_plan *plan, double *price_host, double *stderr_host,
+                     double *mart_resid_host, double *mart_se_host, double *n_itm_host,
+                     void *stream) {
+    if (!plan) return fail(LLL_EINVAL, "plan is NULL");
+    if (!plan->executed) return fail(LLL_EINVAL, "plan has not been executed");
+    const size_t N = plan->N, S = plan->S;
+    std::vector<double> res(3 * N * S + 2 * N);
+    hipStream_t st = as_stream(stream);
+    hipError_t e = hipMemcpyAsync(res.data(), plan->d.results, res.size() * sizeof(double),
+                                  hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "reading results");
+    const double *price = res.data(), *se = price + N * S, *itm = se + N * S;
+    const double *mart = itm + N * S, *mse = mart + N;
+    if (price_host) std::memcpy(price_host, price, N * S * sizeof(double));
+    if (stderr_host) std::memcpy(stderr_host, se, N * S * sizeof(double));
+    if (n_itm_host) std::memcpy(n_itm_host, itm, N * S * sizeof(double));
+    if (mart_resid_host) std::memcpy(mart_resid_host, mart, N * sizeof(double));
+    if (mart_se_host) std::memcpy(mart_se_host, mse, N * sizeof(double));
+    if (!finite_all(price, N * S) || !finite_all(se, N * S))
+        return fail(LLL_ENUMERIC, "non-finite caplet price or standard error");
+    return LLL_OK;
+}
+
+int lll_plan_sums(lll_plan *plan, double *sums_host, void *stream) {
+    if (!plan || !sums_host) return fail(LLL_EINVAL, "NULL argument");
+    if (!plan->executed) return fail(LLL_EINVAL, "plan has not been executed");
+    const size_t n = (size_t)plan->N * (3 * plan->S + 2);
+    hipStream_t st = as_stream(stream);
+    hipError_t e = hipMemcpyAsync(sums_host, plan->d.sums, n * sizeof(double),
+                                  hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "reading sums");
+    return LLL_OK;
+}
+
+int lll_plan_partials(lll_plan *plan, double *partials_host, int64_t capacity, void *stream) {
+    if (!plan || !partials_host) return fail(LLL_EINVAL, "NULL argument");
+    if (!plan->executed) return fail(LLL_EINVAL, "plan has not been executed");
+    const int64_t waves = (plan->last_n_paths + lll::kWaveSize - 1) / lll::kWaveSize;
+    const int64_t n = waves * plan->N * (3 * plan->S + 2);
+    if (capacity < n) return fail(LLL_EINVAL, "capacity %lld < %lld", (long long)capacity,
+                                  (long long)n);
+    hipStream_t st = as_stream(stream);
+    hipError_t e = hipMemcpyAsync(partials_host, plan->d.partials, n * sizeof(double),
+                                  hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "reading partials");
+    return LLL_OK;
+}
+
+int lll_price_caplets(const lll_term_structure *ts, int64_t n_paths, int scheme, uint64_t seed,
+                      int precision, double *price_host, double *stderr_host,
+                      double *mart_resid_host, void *stream) {
+    lll_plan *plan = nullptr;
+    int rc = lll_plan_create(ts, precision, n_paths, &plan);
+    if (rc != LLL_OK) return rc;
+    rc = lll_plan_execute(plan, scheme, n_paths, 0, seed, nullptr, stream);
+    if (rc == LLL_OK)
+        rc = lll_plan_results(plan, price_host, stderr_host, mart_resid_host, nullptr, nullptr,
+                              stream);
+    lll_plan_destroy(plan);
+    return rc;
+}
+
+int lll_philox(const uint32_t *ctr_host, const uint32_t *key_host, int64_t n, uint32_t *out_host,
+               void *stream) {
+    if (!ctr_host || !key_host || !out_host) return fail(LLL_EINVAL, "NULL argument");
+    if (n < 1 || n > ((int64_t)1 << 28)) return fail(LLL_EINVAL, "n=%lld out of range", (long long)n);
+    uint32_t *d = nullptr;
+    hipError_t e = hipMalloc(&d, (size_t)n * 10 * sizeof(uint32_t));
+    if (e != hipSuccess) return hip_fail(e, "allocating Philox buffers");
+    hipStream_t st = as_stream(stream);
+    uint32_t *dc = d, *dk = d + 4 * n, *dout = d + 6 * n;
+    e = hipMemcpyAsync(dc, ctr_host, (size_t)n * 4 * sizeof(uint32_t), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(dk, key_host, (size_t)n * 2 * sizeof(uint32_t), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = lll::launch_philox(dc, dk, n, dout, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(out_host, dout, (size_t)n * 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(d);
+    if (e != hipSuccess) return hip_fail(e, "Philox kernel");
+    return LLL_OK;
+}
+
+int lll_plan_increments(lll_plan *plan, int k, int64_t p0, int64_t n, uint64_t seed,
+                        double *V_host, double *dH_host, void *stream) {
+    if (!plan || !V_host || !dH_host) return fail(LLL_EINVAL, "NULL argument");
+    if (k < 0 || k >= plan->K) return fail(LLL_EINVAL, "step %d outside 0..%d", k, plan->K - 1);
+    if (n < 1 || n > ((int64_t)1 << 28) || p0 < 0) return fail(LLL_EINVAL, "bad path range");
+    hipStream_t st = as_stream(stream);
+    hipError_t e = lll::launch_precompute(*plan, st);
+    if (e != hipSuccess) return hip_fail(e, "precompute launch");
+    double *d = nullptr;
+    e = hipMalloc(&d, (size_t)n * 2 * sizeof(double));
+    if (e != hipSuccess) return hip_fail(e, "allocating increment buffers");
+    e = lll::launch_increments(*plan, k, p0, n, seed, d, d + n, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(V_host, d, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(dH_host, d + n, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(d);
+    if (e != hipSuccess) return hip_fail(e, "increment kernel");
+    return LLL_OK;
+}
+
+int lll_plan_tables(lll_plan *plan, double *x_host, double *w_host, double *kappa_host,
+                    double *E_host, double *b0_host, void *stream) {
+    if (!plan) return fail(LLL_EINVAL, "plan is NULL");
+    hipStream_t st = as_stream(stream);
+    hipError_t e = lll::launch_precompute(*plan, st);
+    if (e != hipSuccess) return hip_fail(e, "precompute launch");
+    const size_t K = plan->K, N = plan->N, Q = lll::kQSize;
+    auto D2H = [&](double *dst, const double *src, size_t n) {
+        if (dst && e == hipSuccess)
+            e = hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToHost, st);
+    };
+    D2H(x_host, plan->d.x, Q);
+    D2H(w_host, plan->d.w, Q);
+    D2H(kappa_host, plan->d.kappa, K * N);
+    D2H(E_host, plan->d.E, K * N * Q);
+    D2H(b0_host, plan->d.b0, K * N);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "reading tables");
+    return LLL_OK;
+}
+
+int lll_plan_drift(lll_plan *plan, int k, const double *L_host, int64_t n, double *b_host,
+                   void *stream) {
+    if (!plan || !L_host || !b_host) return fail(LLL_EINVAL, "NULL argument");
+    if (k < 0 || k >= plan->K) return fail(LLL_EINVAL, "step %d outside 0..%d", k, plan->K - 1);
+    if (n < 1 || n > ((int64_t)1 << 24)) return fail(LLL_EINVAL, "n=%lld out of range", (long long)n);
+    const int first = k / plan->s;
+    for (int64_t i = 0; i < n; ++i)
+        for (int r = first; r < plan->N; ++r)
+            if (!(L_host[i * plan->N + r] > 0.0) || !std::isfinite(L_host[i * plan->N + r]))
+                return fail(LLL_EINVAL, "rates must be positive and finite");
+    hipStream_t st = as_stream(stream);
+    hipError_t e = lll::launch_precompute(*plan, st);
+    if (e != hipSuccess) return hip_fail(e, "precompute launch");
+    const size_t bytes = (size_t)n * plan->N * sizeof(double);
+    double *d = nullptr;
+    e = hipMalloc(&d, 2 * bytes);
+    if (e != hipSuccess) return hip_fail(e, "allocating drift buffers");
+    double *dL = d, *db = d + (size_t)n * plan->N;
+    e = hipMemcpyAsync(dL, L_host, bytes, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = lll::launch_drift(*plan, k, dL, n, db, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(b_host, db, bytes, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(d);
+    if (e != hipSuccess) return hip_fail(e, "drift kernel");
+    return LLL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,9 @@
+// bucket_f64_n24.hip -- path kernel instantiations for double state, 24 rate slots.
+#define LLL_BUCKET_TU
+#include "path_kernel.hpp"
+
+namespace lll {
+namespace detail {
+LLL_BUCKET_DECL(, double, 24)
+}  // namespace detail
+}  // namespace lll

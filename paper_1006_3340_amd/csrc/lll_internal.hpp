@@ -1,0 +1,81 @@
+// lll_internal.hpp -- host-side plan and kernel launchers (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "lll.h"
+
+namespace lll {
+
+constexpr int kWaveSize = 64;  // CDNA wavefront
+constexpr int kQSize = 64;     // quadrature nodes
+
+// Smallest register bucket holding N rates.  Rates live in register slots
+// off .. off + N - 1 with off = nmax - N, so that the live rates of every
+// period are a suffix of the bucket and all slot indices are compile-time.
+int bucket_for(int n_rates);
+
+struct DeviceTables {
+    // FP64 inputs (device)
+    double *tenor = nullptr, *delta = nullptr, *L0 = nullptr, *vol = nullptr, *strikes = nullptr;
+    // FP64 precompute, inspection layout
+    double *x = nullptr, *w = nullptr;          // [Q]
+    double *kappa = nullptr;                    // [K][N]
+    double *E = nullptr;                        // [K][N][Q]
+    double *b0 = nullptr;                       // [K][N]
+    double *steps = nullptr;                    // [N][4] per-period increment constants
+    double *lam_pm = nullptr;                   // [2] Lambda_+, Lambda_-
+    // path-kernel layout in the plan's precision (slot columns, nmax wide)
+    void *ew = nullptr;        // [K][Q][nmax][2]  (E, W E)
+    void *lam = nullptr;       // [K][nmax]
+    void *drift0 = nullptr;    // [K][nmax]  -kappa dt
+    void *frozen = nullptr;    // [K][nmax]  b0 dt
+    void *dt = nullptr;        // [K]
+    void *cinv = nullptr;      // [nmax]  1 / (delta L0)
+    double *L0s = nullptr, *deltas = nullptr;   // [nmax] FP64 slot layout
+    // reduction
+    double *partials = nullptr;  // [max_waves][N][NSTAT]
+    double *chunks = nullptr;    // [max_chunks][N*NSTAT]
+    double *sums = nullptr;      // [N][NSTAT]
+    double *results = nullptr;   // price[N*S], se[N*S], itm[N*S], mart[N], mart_se[N]
+};
+
+}  // namespace lll
+
+struct lll_plan {
+    int N = 0, s = 0, S = 0, K = 0, driver = 0, precision = 0, nmax = 0, off = 0;
+    uint32_t struct_id = 0;
+    double B0_T1 = 0, alpha = 0, beta = 0, delta_nig = 0, c = 0;
+    int64_t max_paths = 0, max_waves = 0, max_chunks = 0;
+    int device = 0;
+    std::vector<double> tenor, delta, L0, vol, strikes;
+    lll::DeviceTables d;
+    int64_t last_n_paths = 0;
+    bool executed = false;
+    bool timing = false, timed = false;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+
+namespace lll {
+
+constexpr int kStatBase = 3;  // NSTAT = 3 S + 2
+
+// precompute.hip
+hipError_t launch_precompute(const lll_plan &p, hipStream_t st);
+
+// paths.hip
+hipError_t launch_paths(const lll_plan &p, int scheme, int64_t n_paths, int64_t path_offset,
+                        uint64_t seed, double *path_fix, hipStream_t st);
+hipError_t launch_reduce(const lll_plan &p, int64_t n_paths, hipStream_t st);
+hipError_t launch_drift(const lll_plan &p, int k, const double *L_dev, int64_t n, double *b_dev,
+                        hipStream_t st);
+hipError_t launch_increments(const lll_plan &p, int k, int64_t p0, int64_t n, uint64_t seed,
+                             double *V_dev, double *dH_dev, hipStream_t st);
+hipError_t launch_philox(const uint32_t *ctr_dev, const uint32_t *key_dev, int64_t n,
+                         uint32_t *out_dev, hipStream_t st);
+
+}  // namespace lll

@@ -1,0 +1,80 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function include/lll.h declares, and rejects malformed inputs with the
+documented status codes before touching the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "lll.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lll_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_header_functions():
+    import paper_1006_3340_amd._lib as L
+    lib = L.load()
+    names = header_functions()
+    assert len(names) >= 13
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(L.EXPORTS)
+
+
+def test_version_string():
+    import paper_1006_3340_amd as lll
+    assert "gfx950" in lll.version()
+
+
+def _expect(code, ts, **kw):
+    import paper_1006_3340_amd as lll
+    with pytest.raises(lll.LLLError) as ei:
+        lll.Plan(ts, **kw)
+    assert ei.value.code == code, str(ei.value)
+    return str(ei.value)
+
+
+def test_validation_errors():
+    EINVAL, EMOMENT, EUNSUP = -1, -2, -5
+    ts = workloads.plain_fp64()
+    _expect(EINVAL, ts.copy(L0=-ts.L0))
+    L0 = ts.L0.copy(); L0[3] = np.nan
+    _expect(EINVAL, ts.copy(L0=L0))
+    tenor = ts.tenor.copy(); tenor[4] = tenor[3]
+    _expect(EINVAL, ts.copy(tenor=tenor))
+    delta = ts.delta.copy(); delta[2] = 0.3
+    _expect(EINVAL, ts.copy(delta=delta))
+    _expect(EINVAL, ts.copy(alpha=3.0, beta=-4.0))          # alpha <= |beta|
+    _expect(EINVAL, ts.copy(delta_nig=0.0))
+    _expect(EINVAL, ts.copy(steps_per_period=0, vol=ts.vol[:0]))
+    vol = ts.vol.copy(); vol[5, 7] = np.inf
+    _expect(EINVAL, ts.copy(vol=vol))
+    _expect(EINVAL, ts.copy(driver=7))
+    _expect(EINVAL, ts.copy(driver=1, c=-1.0))
+    _expect(EINVAL, ts, max_paths=0)
+    _expect(EINVAL, ts, precision=5)
+    _expect(EINVAL, ts.copy(strikes=np.zeros((10, 9))))  # more than 8 strikes
+    # drift integral diverges: the live vols sum beyond alpha - beta
+    msg = _expect(EMOMENT, ts.copy(vol=ts.vol * 20.0))
+    assert "Lambda" in msg
+    # the paper's own example sits just inside the moment condition
+    k = workloads.kluge_example()
+    _expect(EMOMENT, k.copy(vol=k.vol * 1.05))
+    # FP64 path kernel only up to 24 rates
+    _expect(EUNSUP, workloads.learned_drift(), precision=1)
+    big = workloads.make_structure(41, 0.25, 0.03, 2, lambda t, T, r: 0.1, [1.0])
+    _expect(EINVAL, big)
+
+
+def test_inspection_entry_points_validate():
+    import paper_1006_3340_amd as lll
+    with pytest.raises(lll.LLLError):
+        lll.philox(np.zeros((0, 4), np.uint32), np.zeros((0, 2), np.uint32))

@@ -1,0 +1,276 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Tolerances (derived from the arithmetic, not tuned):
+
+* Philox words and the uniform map are integer work: bit-exact.
+* Driver increments are FP64 on both sides; the device writes the inverse-
+  Gaussian root without cancellation, the oracle in its textbook form, which
+  loses up to ~log10(m/x) digits: 1e-11 relative to the sum of the magnitudes
+  of the terms of dH.  The subordinator branch is decided in FP64 on both
+  sides (same decision precision).
+* FP64 tables: nodes, weights and E to 1e-13 relative; the cumulant to the
+  cancellation bound of the oracle's closed form.
+* FP64 path kernel vs oracle: per-path state errors ~1e-15 relative grow over
+  N*s steps and are amplified by L/|L - K| near the strike; 1e-10 relative
+  per caplet leaves two orders of margin.
+* FP32 path kernel vs oracle: the metric's 1e-4 relative per caplet, applied
+  where the oracle has at least 100 in-the-money paths; otherwise the absolute
+  error must stay below 1e-4 times the at-the-money price of the same caplet
+  (a single path can dominate a deep out-of-the-money caplet).
+"""
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+FULL, PICARD, FROZEN = 0, 1, 2
+SCHEMES = (FULL, PICARD, FROZEN)
+
+
+def _oracle(oracle_mod, ts, seed=1):
+    return oracle_mod.Oracle(ts, seed=seed)
+
+
+def test_philox_words_bit_exact(gpu_lib, oracle_mod):
+    rng = np.random.default_rng(11)
+    ctr = rng.integers(0, 2**32, size=(2048, 4), dtype=np.uint64).astype(np.uint32)
+    key = rng.integers(0, 2**32, size=(2048, 2), dtype=np.uint64).astype(np.uint32)
+    ctr[:4] = [[0, 0, 0, 0], [0xFFFFFFFF] * 4, [399, 2**20 - 1, 0, 63], [7, 5, 1, 1 << 24]]
+    key[:4] = [[0, 0], [0xFFFFFFFF] * 2, [1, 0], [1, 0]]
+    got = gpu_lib.philox(ctr, key)
+    for i in range(len(ctr)):
+        ref = oracle_mod.philox4x32_10(ctr[i], key[i])
+        assert np.array_equal(got[i], ref), (i, got[i], ref)
+
+
+@pytest.mark.parametrize("wl", ["plain_n10", "gpu_n20", "kluge_n9"])
+def test_increments_match_oracle(gpu_lib, oracle_mod, wl):
+    ts = workloads.WORKLOADS[wl]()
+    o = _oracle(oracle_mod, ts, seed=3)
+    with gpu_lib.Plan(ts, max_paths=1024) as plan:
+        for k in (0, ts.steps_per_period + 1, ts.n_steps - 1):
+            n, p0 = 50000, 123456789
+            V, dH = plan.increments(k, p0, n, seed=3)
+            Vo, dHo = o.increments(k, p0, n)
+            assert np.all(np.abs(V - Vo) <= 1e-11 * np.abs(Vo)), k
+            gamma = np.sqrt(ts.alpha**2 - ts.beta**2)
+            mu_dt = -ts.delta_nig * ts.beta / gamma * o.dt[k]
+            # magnitudes of the three terms mu dt, beta V and sqrt(V) z2 of dH
+            mag = abs(mu_dt) + abs(ts.beta) * Vo + np.abs(dHo - mu_dt - ts.beta * Vo)
+            assert np.all(np.abs(dH - dHo) <= 1e-11 * mag), k
+
+
+def test_brownian_increments_match_oracle(gpu_lib, oracle_mod):
+    ts = workloads.brownian(N=5, c=0.8)
+    o = _oracle(oracle_mod, ts, seed=4)
+    with gpu_lib.Plan(ts, max_paths=64) as plan:
+        V, dH = plan.increments(3, 0, 20000, seed=4)
+        _, dHo = o.increments(3, 0, 20000)
+        assert np.all(V == 0.0)
+        assert np.allclose(dH, dHo, rtol=1e-13, atol=1e-15)
+
+
+@pytest.mark.parametrize("wl", ["plain_n10", "gpu_n20", "mlp_n40", "kluge_n9"])
+def test_precompute_tables_match_oracle(gpu_lib, oracle_mod, wl):
+    ts = workloads.WORKLOADS[wl]()
+    o = _oracle(oracle_mod, ts)
+    with gpu_lib.Plan(ts, max_paths=64) as plan:
+        t = plan.tables()
+    assert np.allclose(t["x"], o.x, rtol=1e-13, atol=0)
+    assert np.allclose(t["w"], o.W, rtol=1e-12, atol=0)
+    s = ts.steps_per_period
+    live = np.array([[r >= k // s for r in range(ts.n_rates)] for k in range(ts.n_steps)])
+    # cumulant: the oracle's closed form cancels |mu u| + delta (gamma + sqrt(.)) down to kappa
+    gamma = np.sqrt(ts.alpha**2 - ts.beta**2)
+    u = ts.vol
+    sq = np.sqrt(np.maximum(ts.alpha**2 - (ts.beta + u) ** 2, 0.0))
+    scale = np.abs(ts.delta_nig * ts.beta / gamma * u) + ts.delta_nig * (gamma + sq)
+    assert np.all(np.abs(t["kappa"] - o.kappa)[live] <= (8 * 2.0**-53 * scale + 1e-15 * np.abs(o.kappa))[live])
+    assert np.all(t["kappa"][~live] == 0.0)
+    assert np.allclose(t["E"], o.E, rtol=1e-13, atol=1e-300)
+    # frozen drift: suffix recursion vs literal products (plus the cumulant tolerance)
+    err = np.abs(t["b0"] - o.b0)[live]
+    assert np.all(err <= (1e-12 * np.abs(o.b0) + 8 * 2.0**-53 * scale)[live])
+
+
+@pytest.mark.parametrize("precision,rtol", [(1, 1e-12), (0, 1e-5)])
+@pytest.mark.parametrize("wl", ["plain_n10", "gpu_n20", "kluge_n9"])
+def test_drift_matches_oracle(gpu_lib, oracle_mod, wl, precision, rtol):
+    ts = workloads.WORKLOADS[wl]()
+    o = _oracle(oracle_mod, ts)
+    rng = np.random.default_rng(5)
+    with gpu_lib.Plan(ts, precision=precision, max_paths=64) as plan:
+        for k in (0, ts.steps_per_period * 3 + 2, ts.n_steps - 1):
+            L = ts.L0[None, :] * np.exp(rng.normal(0.0, 0.25, size=(37, ts.n_rates)))
+            b = plan.drift(k, L)
+            first = k // ts.steps_per_period
+            for i in range(L.shape[0]):
+                ref = o.drift(k, L[i])
+                assert np.all(np.abs(b[i, first:] - ref[first:]) <= rtol * np.abs(ref[first:])), \
+                    (k, i, b[i, first:], ref[first:])
+                assert np.all(b[i, :first] == 0.0)
+
+
+def _check_prices(got, ref, ts, rtol, itm_floor=100):
+    """Per-caplet relative error; deep out-of-the-money caplets with fewer than
+    `itm_floor` in-the-money oracle paths use 1e-4 x the ATM price as floor."""
+    price, rp = got["price"], ref["price"]
+    atm_col = int(np.argmin(np.abs(ts.strikes[0] / ts.L0[0] - 1.0)))
+    for i in range(ts.n_rates):
+        for j in range(ts.n_strikes):
+            err = abs(price[i, j] - rp[i, j])
+            if ref["n_itm"][i, j] >= itm_floor:
+                assert err <= rtol * abs(rp[i, j]), (i, j, price[i, j], rp[i, j])
+            else:
+                assert err <= rtol * abs(rp[i, atm_col]) + 1e-300, (i, j, price[i, j], rp[i, j])
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("wl,n_paths", [("plain_n10", 10000), ("gpu_n20", 2000), ("kluge_n9", 3001)])
+def test_price_fp64_kernel_matches_oracle(gpu_lib, oracle_mod, wl, n_paths, scheme):
+    ts = workloads.WORKLOADS[wl]()
+    o = _oracle(oracle_mod, ts)
+    ref = o.price(scheme, n_paths)
+    with gpu_lib.Plan(ts, precision=1, max_paths=n_paths) as plan:
+        plan.execute(scheme, n_paths, seed=1)
+        got = plan.results()
+    assert np.array_equal(got["n_itm"], ref["n_itm"])
+    assert np.allclose(got["price"], ref["price"], rtol=1e-10, atol=0)
+    assert np.allclose(got["stderr"], ref["stderr"], rtol=1e-8, atol=1e-300)
+    assert np.allclose(got["mart_resid"], ref["mart_resid"], rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("wl,n_paths", [("plain_n10", 10000), ("gpu_n20", 4173),
+                                        ("kluge_n9", 10000), ("mlp_n40", 700)])
+def test_price_fp32_kernel_matches_oracle(gpu_lib, oracle_mod, wl, n_paths, scheme):
+    ts = workloads.WORKLOADS[wl]()
+    o = _oracle(oracle_mod, ts)
+    ref = o.price(scheme, n_paths)
+    with gpu_lib.Plan(ts, precision=0, max_paths=n_paths) as plan:
+        plan.execute(scheme, n_paths, seed=1)
+        got = plan.results()
+    _check_prices(got, ref, ts, 1e-4)
+    # FP32 rates can land on the other side of a strike on a handful of paths
+    assert np.all(np.abs(got["n_itm"] - ref["n_itm"]) <= 3 + 1e-4 * n_paths)
+
+
+def test_full_size_sampled_paths_and_reduction(gpu_lib, oracle_mod):
+    """The bench configuration (N=20, 2^20 paths, FULL and PICARD, FP32): sampled
+    per-path fixings against the oracle, and the reduction against the mean of
+    the per-path payoffs recomputed on the host."""
+    import torch
+    ts = workloads.gpu_scale()
+    n = 1 << 20
+    o = _oracle(oracle_mod, ts)
+    rng = np.random.default_rng(2)
+    sample = np.sort(rng.choice(n, size=24, replace=False))
+    sample[0], sample[-1] = 0, n - 1
+    fix = torch.empty((n, 2 * ts.n_rates), dtype=torch.float64, device="cuda")
+    with gpu_lib.Plan(ts, precision=0, max_paths=n) as plan:
+        for scheme in (FULL, PICARD):
+            plan.execute(scheme, n, seed=1, path_fix=fix)
+            got = plan.results()
+            torch.cuda.synchronize()
+            f = fix.cpu().numpy()
+            Lg, Dg = f[:, 0::2], f[:, 1::2]
+            Lo, Do = o.paths(scheme, sample)
+            assert np.all(np.abs(Lg[sample] / Lo - 1.0) < 2e-5), scheme
+            assert np.all(np.abs(Dg[sample] / Do - 1.0) < 2e-5), scheme
+            pay = Dg[:, :, None] * np.maximum(Lg[:, :, None] - ts.strikes[None], 0.0)
+            B0T = ts.B0_T1 / np.prod(1.0 + ts.delta * ts.L0)
+            host_price = ts.delta[:, None] * B0T * pay.mean(axis=0)
+            assert np.allclose(got["price"], host_price, rtol=1e-12, atol=0)
+
+
+def test_deterministic_and_split_range(gpu_lib):
+    ts = workloads.gpu_scale()
+    n = 1 << 16
+    with gpu_lib.Plan(ts, precision=0, max_paths=n) as plan:
+        plan.execute(FULL, n, seed=7)
+        a, pa = plan.sums(), plan.partials()
+        plan.execute(FULL, n, seed=7)
+        b, pb = plan.sums(), plan.partials()
+        assert np.array_equal(a, b) and np.array_equal(pa, pb)
+        half = n // 2
+        plan.execute(FULL, half, seed=7, path_offset=0)
+        p1 = plan.partials()
+        plan.execute(FULL, half, seed=7, path_offset=half)
+        p2 = plan.partials()
+        assert np.array_equal(np.concatenate([p1, p2]), pa)
+        plan.execute(FULL, n, seed=8)
+        assert not np.array_equal(plan.sums(), a)
+
+
+@pytest.mark.parametrize("n_paths", [1, 63, 65, 257])
+def test_ragged_path_counts(gpu_lib, oracle_mod, n_paths):
+    ts = workloads.plain_fp64()
+    o = _oracle(oracle_mod, ts)
+    ref = o.price(FULL, n_paths)
+    with gpu_lib.Plan(ts, precision=1, max_paths=1024) as plan:
+        plan.execute(FULL, n_paths, seed=1)
+        got = plan.results()
+    assert np.allclose(got["price"], ref["price"], rtol=1e-10, atol=1e-300)
+    assert np.array_equal(got["n_itm"], ref["n_itm"])
+
+
+@pytest.mark.parametrize("N,s", [(1, 1), (1, 7), (2, 1), (9, 3), (17, 2), (24, 2)])
+def test_shapes_fp64(gpu_lib, oracle_mod, N, s):
+    ts = workloads.make_structure(N, 0.25, 0.02 + 0.001 * np.arange(N), s,
+                                  workloads.exp_decay_vol(), [0.9, 1.0, 1.1])
+    o = _oracle(oracle_mod, ts)
+    for scheme in SCHEMES:
+        ref = o.price(scheme, 999)
+        with gpu_lib.Plan(ts, precision=1, max_paths=999) as plan:
+            plan.execute(scheme, 999, seed=1)
+            got = plan.results()
+        assert np.allclose(got["price"], ref["price"], rtol=1e-10, atol=1e-300), (N, s, scheme)
+
+
+@pytest.mark.parametrize("N", [25, 33, 40])
+def test_large_buckets_fp32(gpu_lib, oracle_mod, N):
+    ts = workloads.make_structure(N, 0.25, 0.03 + 0.0005 * np.arange(N), 3,
+                                  workloads.exp_decay_vol(), [1.0])
+    o = _oracle(oracle_mod, ts)
+    for scheme in SCHEMES:
+        ref = o.price(scheme, 600)
+        with gpu_lib.Plan(ts, precision=0, max_paths=600) as plan:
+            plan.execute(scheme, 600, seed=1)
+            got = plan.results()
+        _check_prices(got, ref, ts, 1e-4)
+
+
+def test_zero_vol_and_brownian(gpu_lib, oracle_mod):
+    ts = workloads.make_structure(7, 0.5, 0.03 + 0.004 * np.arange(7), 4, lambda t, T, r: 0.0,
+                                  [0.7, 1.0, 1.3])
+    B = ts.B0_T1 / np.cumprod(1.0 + ts.delta * ts.L0)
+    exact = ts.delta[:, None] * B[:, None] * np.maximum(ts.L0[:, None] - ts.strikes, 0.0)
+    for prec in (0, 1):
+        with gpu_lib.Plan(ts, precision=prec, max_paths=300) as plan:
+            for scheme in SCHEMES:
+                plan.execute(scheme, 300)
+                assert np.allclose(plan.results()["price"], exact, rtol=1e-12, atol=1e-18)
+    tb = workloads.brownian(N=6)
+    o = _oracle(oracle_mod, tb)
+    for scheme in SCHEMES:
+        ref = o.price(scheme, 5000)
+        with gpu_lib.Plan(tb, precision=1, max_paths=5000) as plan:
+            plan.execute(scheme, 5000)
+            got = plan.results()
+        assert np.allclose(got["price"], ref["price"], rtol=1e-10, atol=1e-300)
+
+
+def test_execute_errors(gpu_lib):
+    ts = workloads.plain_fp64()
+    with gpu_lib.Plan(ts, max_paths=100) as plan:
+        for bad in (dict(scheme=FULL, n_paths=0), dict(scheme=FULL, n_paths=101),
+                    dict(scheme=9, n_paths=10)):
+            with pytest.raises(gpu_lib.LLLError) as ei:
+                plan.execute(**bad)
+            assert ei.value.code == -1
+        with pytest.raises(gpu_lib.LLLError):
+            plan.results()  # nothing executed yet
+        plan.execute(FULL, 100)
+        assert np.all(np.isfinite(plan.results()["price"]))
