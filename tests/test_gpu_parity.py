@@ -106,14 +106,21 @@ def test_drift_matches_oracle(gpu_lib, oracle_mod, wl, precision, rtol):
     ts = workloads.WORKLOADS[wl]()
     o = _oracle(oracle_mod, ts)
     rng = np.random.default_rng(5)
+    gamma = np.sqrt(ts.alpha**2 - ts.beta**2)
     with gpu_lib.Plan(ts, precision=precision, max_paths=64) as plan:
         for k in (0, ts.steps_per_period * 3 + 2, ts.n_steps - 1):
             L = ts.L0[None, :] * np.exp(rng.normal(0.0, 0.25, size=(37, ts.n_rates)))
             b = plan.drift(k, L)
             first = k // ts.steps_per_period
+            # the oracle's closed-form cumulant carries 8 eps x (|mu u| + delta (gamma + s))
+            u = ts.vol[k]
+            sq = np.sqrt(np.maximum(ts.alpha**2 - (ts.beta + u) ** 2, 0.0))
+            kap_tol = 8 * 2.0**-53 * (np.abs(ts.delta_nig * ts.beta / gamma * u)
+                                      + ts.delta_nig * (gamma + sq))
             for i in range(L.shape[0]):
                 ref = o.drift(k, L[i])
-                assert np.all(np.abs(b[i, first:] - ref[first:]) <= rtol * np.abs(ref[first:])), \
+                tol = rtol * np.abs(ref[first:]) + kap_tol[first:]
+                assert np.all(np.abs(b[i, first:] - ref[first:]) <= tol), \
                     (k, i, b[i, first:], ref[first:])
                 assert np.all(b[i, :first] == 0.0)
 
