@@ -75,8 +75,11 @@ def main(argv=None) -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--paths", type=int, default=1 << 20)
     ap.add_argument("--schemes", default="full,picard")
-    ap.add_argument("--cpu-sample", type=int, default=2048,
+    ap.add_argument("--cpu-sample", type=int, default=65536,
                     help="paths of the oracle timing sample (0 skips it)")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="also run one device-to-device copy of this many MiB (a kernel of "
+                         "known traffic for calibrating HBM counters)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
@@ -117,6 +120,11 @@ def main(argv=None) -> int:
     for _ in range(3):
         one_step(rec)
     torch.cuda.synchronize()
+    if args.copy_mib > 0:
+        src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
     res = plan.results(stream)
     if not np.all(np.isfinite(res["price"])):
         print(json.dumps({"error": "non-finite prices"}))
