@@ -27,6 +27,24 @@ sys.path.insert(0, ROOT)
 import workloads  # noqa: E402
 
 PEAK_FP32 = 157.3e12   # MI355X vector FP32, FLOP/s
+
+# HBM bytes per path-kernel launch from rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE runs of this benchmark, each scaled by the same counter's reading
+# for a 1 GiB device copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0), keyed by the
+# hash of the kernel sources they were taken on; any other hash reports null.
+TRAFFIC_BYTES = {"ef0c815fd706d438": {"full": 219397837, "picard": 279377612}}
+KERNEL_SOURCES = ["paper_1006_3340_amd/csrc/path_kernel.hpp",
+                  "paper_1006_3340_amd/csrc/lll_device.hpp",
+                  "paper_1006_3340_amd/_build.py"]
+
+
+def kernel_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 Q = 64
 METRIC = "path-steps/s: full Euler vs Picard vs MLP drift, at <=1e-4 rel caplet error"
 
@@ -166,7 +184,8 @@ def main(argv=None) -> int:
         "roofline": {"bound": "alu", "kernel": f"path_kernel<float,24,{dom}>",
                      "achieved": fl_dom / (ms_dom / 1e3) / 1e12, "peak": PEAK_FP32 / 1e12,
                      "unit": "TFLOP/s", "frac": fl_dom / (ms_dom / 1e3) / PEAK_FP32,
-                     "traffic": None},
+                     "traffic": TRAFFIC_BYTES.get(kernel_hash(), {}).get(dom),
+                     "kernel_hash": kernel_hash()},
         "schemes": per_scheme,
         "wall_s": wall,
     }
