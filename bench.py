@@ -86,6 +86,27 @@ def cpu_baseline(ts, n_sample: int, schemes) -> dict:
                       f"({'+'.join(schemes)}) of the same workload, {dt:.1f} s"}
 
 
+def bench_batched(lll, stream, schemes, n_each: int = 1 << 18, reps: int = 2) -> dict:
+    """64 independent structures in one persistent launch: kernel time (HIP events
+    recorded by the library), path-steps/s and FP32 fraction of peak."""
+    structs = workloads.batched()
+    out = {"workload": "batched_64", "n_structures": len(structs), "paths_each": n_each}
+    with lll.Batch(structs, max_paths_each=n_each) as b:
+        b.set_timing(True)
+        for name in schemes:
+            b.execute(lll.SCHEMES[name], n_each, seed=1, stream=stream)  # warmup
+            ms = []
+            for _ in range(reps):
+                b.execute(lll.SCHEMES[name], n_each, seed=1, stream=stream)
+                ms.append(b.timing())
+            t = float(np.mean(ms)) / 1e3
+            steps = sum(ts.n_steps for ts in structs) * n_each
+            fl = sum(flops_per_path(ts, name) for ts in structs) * n_each
+            out[name] = {"kernel_ms": t * 1e3, "path_steps_per_s": steps / t,
+                         "fp32_tflops": fl / t / 1e12, "frac_fp32_peak": fl / t / PEAK_FP32}
+    return out
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,6 +116,8 @@ def main(argv=None) -> int:
     ap.add_argument("--schemes", default="full,picard")
     ap.add_argument("--cpu-sample", type=int, default=65536,
                     help="paths of the oracle timing sample (0 skips it)")
+    ap.add_argument("--batched", type=int, default=1,
+                    help="also time the 64-structure persistent launch (2^18 paths each)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (a kernel of "
                          "known traffic for calibrating HBM counters)")
@@ -189,6 +212,8 @@ def main(argv=None) -> int:
         "schemes": per_scheme,
         "wall_s": wall,
     }
+    if args.batched:
+        out["batched"] = bench_batched(lll, stream, schemes)
     if args.cpu_sample > 0:
         out["cpu_baseline"] = cpu_baseline(ts, args.cpu_sample, schemes)
     plan.close()

@@ -146,6 +146,38 @@ int lll_price_caplets(const lll_term_structure *ts, int64_t n_paths, int scheme,
                       int precision, double *price_host, double *stderr_host,
                       double *mart_resid_host, void *stream);
 
+/* ---- many term structures in one persistent launch ---- */
+
+/* Opaque batch of n_ts independent term structures (FP32 path arithmetic).
+ * Owned by the library. */
+typedef struct lll_batch lll_batch;
+
+/* Validate all n_ts structures (host array ts[n_ts]) and allocate their
+ * device tables and buffers for up to max_paths_each paths per structure.
+ * Each structure's struct_id is its fourth Philox counter word.  Synchronous. */
+int lll_batch_create(const lll_term_structure *ts, int n_ts, int64_t max_paths_each,
+                     lll_batch **batch_out);
+
+/* Price every structure with n_paths_each paths in one persistent kernel
+ * launch on `stream`: work items of 256 paths, longest tenors first, pulled
+ * from a device counter by a grid sized to the GPU's resident capacity; then
+ * each structure's fixed-order reduction.  Blocks the host briefly while the
+ * work list is copied to the device; the pricing itself is asynchronous. */
+int lll_batch_execute(lll_batch *batch, int scheme, int64_t n_paths_each, uint64_t seed,
+                      void *stream);
+
+/* Results of structure `index` of the last batch execute (as lll_plan_results). */
+int lll_batch_results(lll_batch *batch, int index, double *price_host, double *stderr_host,
+                      double *mart_resid_host, double *mart_se_host, double *n_itm_host,
+                      void *stream);
+
+/* Record HIP events around the persistent kernel of later executes; read the
+ * duration (ms) of the last one. */
+int lll_batch_set_timing(lll_batch *batch, int enable);
+int lll_batch_timing(lll_batch *batch, float *ms_host);
+
+int lll_batch_destroy(lll_batch *batch);
+
 /* ---- inspection entry points (used by the parity tests) ---- */
 
 /* Philox-4x32-10 words computed on the device for n counters ctr_host[n][4]

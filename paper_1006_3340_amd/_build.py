@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblll.so")
-SOURCES = ["abi.hip", "precompute.hip", "paths.hip"] + sorted(
+SOURCES = ["abi.hip", "precompute.hip", "paths.hip", "batched.hip"] + sorted(
     f for f in os.listdir(CSRC) if f.startswith("bucket_") and f.endswith(".hip"))
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -31,7 +31,7 @@ PATH_FLAGS = ["-mllvm", "-disable-machine-licm"]
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    extra = PATH_FLAGS if src.startswith("bucket_") else []
+    extra = PATH_FLAGS if src.startswith(("bucket_", "batched")) else []
     cmd = [HIPCC, *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

@@ -26,7 +26,9 @@ N_MAX, N_MAX_FP64, S_MAX, Q = 40, 24, 8, 64
 EXPORTS = ["lll_version", "lll_last_error", "lll_plan_create", "lll_plan_execute",
            "lll_plan_results", "lll_plan_sums", "lll_plan_partials", "lll_plan_destroy",
            "lll_price_caplets", "lll_philox", "lll_plan_increments", "lll_plan_tables",
-           "lll_plan_drift", "lll_plan_set_timing", "lll_plan_timing"]
+           "lll_plan_drift", "lll_plan_set_timing", "lll_plan_timing", "lll_batch_create",
+           "lll_batch_execute", "lll_batch_results", "lll_batch_set_timing", "lll_batch_timing",
+           "lll_batch_destroy"]
 
 
 class LLLError(RuntimeError):
@@ -84,6 +86,12 @@ def load():
     lib.lll_plan_increments.argtypes = [vp, i32, i64, i64, u64, dp, dp, vp]
     lib.lll_plan_tables.argtypes = [vp, dp, dp, dp, dp, dp, vp]
     lib.lll_plan_drift.argtypes = [vp, i32, dp, i64, dp, vp]
+    lib.lll_batch_create.argtypes = [ctypes.POINTER(TermStructureC), i32, i64, ctypes.POINTER(vp)]
+    lib.lll_batch_execute.argtypes = [vp, i32, i64, u64, vp]
+    lib.lll_batch_results.argtypes = [vp, i32, dp, dp, dp, dp, dp, vp]
+    lib.lll_batch_set_timing.argtypes = [vp, i32]
+    lib.lll_batch_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_float)]
+    lib.lll_batch_destroy.argtypes = [vp]
     lib.lll_plan_set_timing.argtypes = [vp, i32]
     lib.lll_plan_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_float)]
     for name in EXPORTS:
@@ -227,6 +235,57 @@ class Plan:
         _check(self.lib.lll_plan_drift(self.h, int(k), _dp(L), L.shape[0], _dp(b),
                                        stream_handle(stream)))
         return b
+
+
+class Batch:
+    """lll_batch: many term structures priced in one persistent launch (FP32)."""
+
+    def __init__(self, structures, max_paths_each: int = 1 << 18):
+        self.lib = load()
+        self._ts = [_TS(ts) for ts in structures]
+        self.shapes = [(ts.n_rates, ts.n_strikes) for ts in structures]
+        arr = (TermStructureC * len(self._ts))(*[t.c for t in self._ts])
+        self._arr = arr
+        h = ctypes.c_void_p()
+        _check(self.lib.lll_batch_create(arr, len(self._ts), int(max_paths_each), ctypes.byref(h)))
+        self.h = h
+        self.n_paths_each = 0
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.lll_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def execute(self, scheme: int, n_paths_each: int, seed: int = 1, stream=None):
+        _check(self.lib.lll_batch_execute(self.h, int(scheme), int(n_paths_each), int(seed),
+                                          stream_handle(stream)))
+        self.n_paths_each = int(n_paths_each)
+
+    def set_timing(self, enable: bool = True):
+        _check(self.lib.lll_batch_set_timing(self.h, 1 if enable else 0))
+
+    def timing(self) -> float:
+        ms = ctypes.c_float()
+        _check(self.lib.lll_batch_timing(self.h, ctypes.byref(ms)))
+        return ms.value
+
+    def results(self, index: int, stream=None) -> dict:
+        N, S = self.shapes[index]
+        price = np.zeros((N, S)); se = np.zeros((N, S)); itm = np.zeros((N, S))
+        mart = np.zeros(N); mse = np.zeros(N)
+        _check(self.lib.lll_batch_results(self.h, int(index), _dp(price), _dp(se), _dp(mart),
+                                          _dp(mse), _dp(itm), stream_handle(stream)))
+        return {"price": price, "stderr": se, "mart_resid": mart, "mart_se": mse,
+                "n_itm": itm, "n_paths": self.n_paths_each}
 
 
 def price_caplets(ts, n_paths: int, scheme: int = FULL, seed: int = 1, precision: int = FP32,

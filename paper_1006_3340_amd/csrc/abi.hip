@@ -119,8 +119,13 @@ const char *lll_version(void) { return "lll-mi355x 0.1 (gfx950)"; }
 
 const char *lll_last_error(void) { return g_last_error.c_str(); }
 
-int lll_plan_create(const lll_term_structure *ts, int precision, int64_t max_paths,
-                    lll_plan **plan_out) {
+}  // extern "C"
+
+namespace {
+
+// Plan creation with an explicit register bucket (0 = smallest that fits N).
+int create_plan(const lll_term_structure *ts, int precision, int64_t max_paths, int nmax,
+                lll_plan **plan_out) {
     if (!plan_out) return fail(LLL_EINVAL, "plan_out is NULL");
     *plan_out = nullptr;
     int rc = validate(ts);
@@ -140,7 +145,7 @@ int lll_plan_create(const lll_term_structure *ts, int precision, int64_t max_pat
     p->K = p->N * p->s;
     p->driver = ts->driver;
     p->precision = precision;
-    p->nmax = lll::bucket_for(p->N);
+    p->nmax = nmax > 0 ? nmax : lll::bucket_for(p->N);
     p->off = p->nmax - p->N;
     p->struct_id = ts->struct_id;
     p->B0_T1 = ts->B0_T1 > 0.0 ? ts->B0_T1 : 1.0 / (1.0 + ts->tenor[0] * ts->L0[0]);
@@ -198,6 +203,15 @@ int lll_plan_create(const lll_term_structure *ts, int precision, int64_t max_pat
     }
     *plan_out = p;
     return LLL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lll_plan_create(const lll_term_structure *ts, int precision, int64_t max_paths,
+                    lll_plan **plan_out) {
+    return create_plan(ts, precision, max_paths, 0, plan_out);
 }
 
 int lll_plan_set_timing(lll_plan *plan, int enable) {
@@ -420,6 +434,122 @@ int lll_plan_drift(lll_plan *plan, int k, const double *L_host, int64_t n, doubl
     (void)hipFree(d);
     if (e != hipSuccess) return hip_fail(e, "drift kernel");
     return LLL_OK;
+}
+
+int lll_batch_destroy(lll_batch *batch) {
+    if (!batch) return LLL_OK;
+    for (lll_plan *p : batch->plans) lll_plan_destroy(p);
+    if (batch->args) (void)hipFree(batch->args);
+    if (batch->items) (void)hipFree(batch->items);
+    if (batch->counter) (void)hipFree(batch->counter);
+    for (int i = 0; i < 2; ++i)
+        if (batch->ev[i]) (void)hipEventDestroy(batch->ev[i]);
+    delete batch;
+    return LLL_OK;
+}
+
+int lll_batch_create(const lll_term_structure *ts, int n_ts, int64_t max_paths_each,
+                     lll_batch **batch_out) {
+    if (!batch_out) return fail(LLL_EINVAL, "batch_out is NULL");
+    *batch_out = nullptr;
+    if (!ts || n_ts < 1 || n_ts > 4096) return fail(LLL_EINVAL, "n_ts=%d outside 1..4096", n_ts);
+    if (max_paths_each < 1 || max_paths_each > ((int64_t)1 << 30))
+        return fail(LLL_EINVAL, "max_paths_each=%lld outside 1..2^30", (long long)max_paths_each);
+    for (int i = 0; i < n_ts; ++i) {
+        int rc = validate(&ts[i]);
+        if (rc != LLL_OK) {
+            std::string msg = "structure " + std::to_string(i) + ": " + g_last_error;
+            return fail(rc, "%s", msg.c_str());
+        }
+    }
+    lll_batch *b = new (std::nothrow) lll_batch();
+    if (!b) return fail(LLL_ENOMEM, "host allocation failed");
+    b->max_paths_each = max_paths_each;
+    for (int i = 0; i < n_ts; ++i) {
+        lll_plan *p = nullptr;
+        int rc = create_plan(&ts[i], LLL_FP32, max_paths_each, LLL_N_MAX, &p);
+        if (rc != LLL_OK) {
+            lll_batch_destroy(b);
+            return rc;
+        }
+        b->plans.push_back(p);
+    }
+    const int64_t blocks = (max_paths_each + 255) / 256;
+    b->max_items = static_cast<int>(blocks * n_ts);
+    hipError_t e = hipMalloc(&b->args, n_ts * lll::batch_args_bytes());
+    if (e == hipSuccess) e = hipMalloc(&b->items, (size_t)b->max_items * lll::batch_item_bytes());
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&b->counter), 256);
+    if (e != hipSuccess) {
+        lll_batch_destroy(b);
+        return fail(LLL_ENOMEM, "device allocation: %s", hipGetErrorString(e));
+    }
+    *batch_out = b;
+    return LLL_OK;
+}
+
+int lll_batch_set_timing(lll_batch *batch, int enable) {
+    if (!batch) return fail(LLL_EINVAL, "batch is NULL");
+    if (enable && !batch->ev[0]) {
+        for (int i = 0; i < 2; ++i) {
+            hipError_t e = hipEventCreate(&batch->ev[i]);
+            if (e != hipSuccess) return hip_fail(e, "creating timing events");
+        }
+    }
+    batch->timing = enable != 0;
+    batch->timed = false;
+    return LLL_OK;
+}
+
+int lll_batch_timing(lll_batch *batch, float *ms_host) {
+    if (!batch || !ms_host) return fail(LLL_EINVAL, "NULL argument");
+    if (!batch->timed) return fail(LLL_EINVAL, "no timed execute recorded");
+    hipError_t e = hipEventSynchronize(batch->ev[1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms_host, batch->ev[0], batch->ev[1]);
+    if (e != hipSuccess) return hip_fail(e, "reading timing events");
+    return LLL_OK;
+}
+
+int lll_batch_execute(lll_batch *batch, int scheme, int64_t n_paths_each, uint64_t seed,
+                      void *stream) {
+    if (!batch) return fail(LLL_EINVAL, "batch is NULL");
+    if (scheme != LLL_FULL && scheme != LLL_PICARD && scheme != LLL_FROZEN)
+        return fail(LLL_EINVAL, "unknown scheme %d", scheme);
+    if (n_paths_each < 1 || n_paths_each > batch->max_paths_each)
+        return fail(LLL_EINVAL, "n_paths_each=%lld outside 1..%lld", (long long)n_paths_each,
+                    (long long)batch->max_paths_each);
+    hipStream_t st = as_stream(stream);
+    hipError_t e = hipSuccess;
+    for (lll_plan *p : batch->plans) {
+        e = lll::launch_precompute(*p, st);
+        if (e != hipSuccess) return hip_fail(e, "precompute launch");
+    }
+    e = lll::batch_prepare(*batch, n_paths_each, seed, st);
+    if (e != hipSuccess) return hip_fail(e, "preparing batch items");
+    if (batch->timing) e = hipEventRecord(batch->ev[0], st);
+    if (e == hipSuccess) e = lll::launch_batched(*batch, scheme, st);
+    if (e != hipSuccess) return hip_fail(e, "batched kernel launch");
+    if (batch->timing) e = hipEventRecord(batch->ev[1], st);
+    if (e != hipSuccess) return hip_fail(e, "recording timing event");
+    for (lll_plan *p : batch->plans) {
+        e = lll::launch_reduce(*p, n_paths_each, st);
+        if (e != hipSuccess) return hip_fail(e, "reduction launch");
+        p->last_n_paths = n_paths_each;
+        p->executed = true;
+    }
+    batch->timed = batch->timing;
+    batch->n_paths_each = n_paths_each;
+    batch->executed = true;
+    return LLL_OK;
+}
+
+int lll_batch_results(lll_batch *batch, int index, double *price_host, double *stderr_host,
+                      double *mart_resid_host, double *mart_se_host, double *n_itm_host,
+                      void *stream) {
+    if (!batch) return fail(LLL_EINVAL, "batch is NULL");
+    if (index < 0 || index >= (int)batch->plans.size())
+        return fail(LLL_EINVAL, "index %d outside 0..%d", index, (int)batch->plans.size() - 1);
+    return lll_plan_results(batch->plans[index], price_host, stderr_host, mart_resid_host,
+                            mart_se_host, n_itm_host, stream);
 }
 
 }  // extern "C"

@@ -60,9 +60,26 @@ struct lll_plan {
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 
+struct lll_batch {
+    std::vector<lll_plan *> plans;   // one per structure, 40-slot bucket, FP32
+    int64_t max_paths_each = 0, n_paths_each = 0;
+    void *args = nullptr;            // device PathArgs<float>[n]
+    void *items = nullptr;           // device work items
+    int *counter = nullptr;          // device work counter
+    int n_items = 0, max_items = 0;
+    bool executed = false, timing = false, timed = false;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+};
+
 namespace lll {
 
 constexpr int kStatBase = 3;  // NSTAT = 3 S + 2
+
+// batched.hip
+size_t batch_item_bytes();
+size_t batch_args_bytes();
+hipError_t batch_prepare(lll_batch &b, int64_t n_paths_each, uint64_t seed, hipStream_t st);
+hipError_t launch_batched(const lll_batch &b, int scheme, hipStream_t st);
 
 // precompute.hip
 hipError_t launch_precompute(const lll_plan &p, hipStream_t st);

@@ -198,11 +198,11 @@ __device__ __forceinline__ void dispatch_payoff(std::integer_sequence<int, Js...
     (void)((j0 == Js ? (payoff<Real, NMAX, Js>(a, m, gid, active, X), 0) : 0) + ...);
 }
 
+// Simulates path `gid` (0-based within the structure; lanes past n_paths run
+// but contribute nothing) through all periods, writing the wave's payoff sums.
+// Every lane of the wavefront must call this together (wave reductions).
 template <typename Real, int NMAX, int SCHEME>
-__global__ void __launch_bounds__(kBlock) path_kernel(PathArgs<Real> a) {
-    const int64_t gid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-    const int64_t wave_first = gid - (threadIdx.x % kWave);
-    if (wave_first >= a.n_paths) return;  // whole wavefront past the end
+__device__ __forceinline__ void simulate(const PathArgs<Real> &a, int64_t gid) {
     const bool active = gid < a.n_paths;
     const int64_t p = a.path_offset + gid;
     const uint32_t p_lo = static_cast<uint32_t>(p);
@@ -232,6 +232,14 @@ __global__ void __launch_bounds__(kBlock) path_kernel(PathArgs<Real> a) {
             ++m;
         }
     }
+}
+
+template <typename Real, int NMAX, int SCHEME>
+__global__ void __launch_bounds__(kBlock) path_kernel(PathArgs<Real> a) {
+    const int64_t gid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    const int64_t wave_first = gid - (threadIdx.x % kWave);
+    if (wave_first >= a.n_paths) return;  // whole wavefront past the end
+    simulate<Real, NMAX, SCHEME>(a, gid);
 }
 
 // Drift of the live rates at step k for given rate vectors (inspection): the

@@ -286,3 +286,57 @@ def test_execute_errors(gpu_lib):
             plan.results()  # nothing executed yet
         plan.execute(FULL, 100)
         assert np.all(np.isfinite(plan.results()["price"]))
+
+
+# ---------------------------------------------------------------------------
+# Many term structures in one persistent launch
+# ---------------------------------------------------------------------------
+
+def test_batched_matches_single_structure_launches(gpu_lib):
+    """All 64 structures: the persistent batched kernel (40-slot bucket) gives the
+    per-structure launches' prices (their own buckets, same arithmetic order)."""
+    structs = workloads.batched()
+    n = 700
+    with gpu_lib.Batch(structs, max_paths_each=n) as b:
+        for scheme in (FULL, PICARD):
+            b.execute(scheme, n, seed=1)
+            for i, ts in enumerate(structs):
+                got = b.results(i)
+                with gpu_lib.Plan(ts, precision=0, max_paths=n) as plan:
+                    plan.execute(scheme, n, seed=1)
+                    ref = plan.results()
+                assert np.allclose(got["price"], ref["price"], rtol=1e-6, atol=1e-300), (scheme, i)
+                assert np.array_equal(got["n_itm"], ref["n_itm"]), (scheme, i)
+
+
+@pytest.mark.parametrize("idx", [0, 1, 2])
+def test_batched_subset_matches_oracle(gpu_lib, oracle_mod, idx):
+    """Structures spanning the N range against the FP64 oracle of each alone."""
+    structs = workloads.batched()
+    order = np.argsort([ts.n_rates for ts in structs])
+    pick = [int(order[0]), int(order[len(order) // 2]), int(order[-1])][idx]
+    n = 512
+    with gpu_lib.Batch(structs, max_paths_each=n) as b:
+        for scheme in (FULL, PICARD):
+            b.execute(scheme, n, seed=1)
+            ts = structs[pick]
+            ref = oracle_mod.Oracle(ts, seed=1).price(scheme, n)
+            _check_prices(b.results(pick), ref, ts, 1e-4)
+
+
+def test_batched_full_size_vs_single(gpu_lib):
+    """Full size (64 x 2^18 paths): batched prices equal single-structure prices
+    for a sample of structures; all structures finite with sane martingale residuals."""
+    structs = workloads.batched()
+    n = 1 << 18
+    with gpu_lib.Batch(structs, max_paths_each=n) as b:
+        b.execute(FULL, n, seed=1)
+        for i, ts in enumerate(structs):
+            r = b.results(i)
+            assert np.all(np.isfinite(r["price"])) and np.all(r["price"] >= 0)
+            assert np.all(np.abs(r["mart_resid"]) < 6 * r["mart_se"] + 1e-6), i
+        for i in (0, 17, 63):
+            with gpu_lib.Plan(structs[i], precision=0, max_paths=n) as plan:
+                plan.execute(FULL, n, seed=1)
+                ref = plan.results()
+            assert np.allclose(b.results(i)["price"], ref["price"], rtol=1e-6, atol=1e-300), i
