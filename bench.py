@@ -114,7 +114,7 @@ def main(argv=None) -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--paths", type=int, default=1 << 20)
     ap.add_argument("--schemes", default="full,picard")
-    ap.add_argument("--cpu-sample", type=int, default=65536,
+    ap.add_argument("--cpu-sample", type=int, default=196608,
                     help="paths of the oracle timing sample (0 skips it)")
     ap.add_argument("--batched", type=int, default=1,
                     help="also time the 64-structure persistent launch (2^18 paths each)")

@@ -146,6 +146,31 @@ int lll_price_caplets(const lll_term_structure *ts, int64_t n_paths, int scheme,
                       int precision, double *price_host, double *stderr_host,
                       double *mart_resid_host, void *stream);
 
+/* ---- pathwise adjoint (caplet Greeks) ---- */
+
+/* Enqueue a FULL-scheme pricing pass of paths 0 .. n_paths-1 on an FP32 plan
+ * (NIG driver) together with the pathwise adjoint of every caplet price
+ * (strike 0) with respect to the initial forwards L(0, T_l) and to a parallel
+ * shift of each rate's volatility curve lambda(., T_l) (all steps k).  The
+ * forward pass checkpoints the live rates at every tenor date; each caplet's
+ * reverse sweep recomputes one accrual period at a time from its checkpoint.
+ * B(0, T_1) is held fixed, so dP/dL0 includes the dependence of B(0, T_*) on
+ * the forwards (paper Section 3.3, eq. (caplet)).  Checkpoint and scratch
+ * buffers (about (N (N+1) / 2 + N + s nmax + s) x 4 bytes per path) are
+ * allocated on the first call and kept by the plan.  Asynchronous. */
+int lll_plan_greeks(lll_plan *plan, int64_t n_paths, uint64_t seed, void *stream);
+
+/* Wait for `stream` and copy the last Greeks pass: price_host[N] (strike 0),
+ * dP_dL0_host[N][N] and dP_dvol_host[N][N], row = caplet, column = input rate.
+ * Any pointer may be NULL. */
+int lll_plan_greeks_results(lll_plan *plan, double *price_host, double *dP_dL0_host,
+                            double *dP_dvol_host, void *stream);
+
+/* One-shot: plan, Greeks pass, results, destroy. */
+int lll_caplet_greeks(const lll_term_structure *ts, int64_t n_paths, uint64_t seed,
+                      double *price_host, double *dP_dL0_host, double *dP_dvol_host,
+                      void *stream);
+
 /* ---- many term structures in one persistent launch ---- */
 
 /* Opaque batch of n_ts independent term structures (FP32 path arithmetic).

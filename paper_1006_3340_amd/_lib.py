@@ -28,7 +28,7 @@ EXPORTS = ["lll_version", "lll_last_error", "lll_plan_create", "lll_plan_execute
            "lll_price_caplets", "lll_philox", "lll_plan_increments", "lll_plan_tables",
            "lll_plan_drift", "lll_plan_set_timing", "lll_plan_timing", "lll_batch_create",
            "lll_batch_execute", "lll_batch_results", "lll_batch_set_timing", "lll_batch_timing",
-           "lll_batch_destroy"]
+           "lll_batch_destroy", "lll_plan_greeks", "lll_plan_greeks_results", "lll_caplet_greeks"]
 
 
 class LLLError(RuntimeError):
@@ -86,6 +86,9 @@ def load():
     lib.lll_plan_increments.argtypes = [vp, i32, i64, i64, u64, dp, dp, vp]
     lib.lll_plan_tables.argtypes = [vp, dp, dp, dp, dp, dp, vp]
     lib.lll_plan_drift.argtypes = [vp, i32, dp, i64, dp, vp]
+    lib.lll_plan_greeks.argtypes = [vp, i64, u64, vp]
+    lib.lll_plan_greeks_results.argtypes = [vp, dp, dp, dp, vp]
+    lib.lll_caplet_greeks.argtypes = [ctypes.POINTER(TermStructureC), i64, u64, dp, dp, dp, vp]
     lib.lll_batch_create.argtypes = [ctypes.POINTER(TermStructureC), i32, i64, ctypes.POINTER(vp)]
     lib.lll_batch_execute.argtypes = [vp, i32, i64, u64, vp]
     lib.lll_batch_results.argtypes = [vp, i32, dp, dp, dp, dp, dp, vp]
@@ -195,6 +198,18 @@ class Plan:
         _check(self.lib.lll_plan_timing(self.h, ms))
         return {"precompute": ms[0], "paths": ms[1], "reduce": ms[2]}
 
+    def greeks(self, n_paths: int, seed: int = 1, stream=None):
+        """Enqueue the FULL pricing pass with the pathwise adjoint (lll_plan_greeks)."""
+        _check(self.lib.lll_plan_greeks(self.h, int(n_paths), int(seed), stream_handle(stream)))
+        self.n_paths = int(n_paths)
+
+    def greeks_results(self, stream=None) -> dict:
+        N = self.N
+        price = np.zeros(N); dL = np.zeros((N, N)); dV = np.zeros((N, N))
+        _check(self.lib.lll_plan_greeks_results(self.h, _dp(price), _dp(dL), _dp(dV),
+                                                stream_handle(stream)))
+        return {"price": price, "dP_dL0": dL, "dP_dvol": dV}
+
     def results(self, stream=None) -> dict:
         N, S = self.N, self.S
         price = np.zeros((N, S)); se = np.zeros((N, S)); itm = np.zeros((N, S))
@@ -299,6 +314,18 @@ def price_caplets(ts, n_paths: int, scheme: int = FULL, seed: int = 1, precision
                                  int(precision), _dp(price), _dp(se), _dp(mart),
                                  stream_handle(stream)))
     return {"price": price, "stderr": se, "mart_resid": mart}
+
+
+def caplet_greeks(ts, n_paths: int, seed: int = 1, stream=None) -> dict:
+    """lll_caplet_greeks: caplet prices (strike 0) and their pathwise derivatives
+    with respect to L(0, T_l) and to parallel shifts of each rate's vol curve."""
+    lib = load()
+    t = _TS(ts)
+    N = ts.n_rates
+    price = np.zeros(N); dL = np.zeros((N, N)); dV = np.zeros((N, N))
+    _check(lib.lll_caplet_greeks(ctypes.byref(t.c), int(n_paths), int(seed), _dp(price), _dp(dL),
+                                 _dp(dV), stream_handle(stream)))
+    return {"price": price, "dP_dL0": dL, "dP_dvol": dV}
 
 
 def philox(ctr: np.ndarray, key: np.ndarray, stream=None) -> np.ndarray:

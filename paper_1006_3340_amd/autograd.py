@@ -1,0 +1,47 @@
+"""torch.autograd.Function over the pathwise caplet adjoint.
+
+``CapletPrice.apply(L0, vol_levels, ts, n_paths, seed)`` returns the caplet
+prices (strike 0 of each caplet) of the term structure ``ts`` with its initial
+forwards replaced by ``L0`` and its vol curves shifted so that
+lambda(t, T_i) = vol_levels[i] + (ts.vol[k, i] - base_levels[i]) (a parallel
+shift of each rate's curve).  The backward pass returns grad_out @ J with the
+Jacobians computed on the GPU by ``lll_plan_greeks``; the forward pass and the
+Jacobians come from the same launch.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _lib
+
+
+def shifted(ts, L0: np.ndarray, levels: np.ndarray, base_levels: np.ndarray):
+    """Copy of ts with forwards L0 and each rate's vol curve shifted by levels - base."""
+    vol = ts.vol.copy()
+    s = ts.steps_per_period
+    for k in range(vol.shape[0]):
+        m = k // s
+        vol[k, m:] += (levels - base_levels)[m:]
+    return ts.copy(L0=np.asarray(L0, dtype=np.float64).copy(), vol=vol)
+
+
+class CapletPrice(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, L0: torch.Tensor, levels: torch.Tensor, ts, n_paths: int, seed: int = 1,
+                base_levels=None):
+        base = np.zeros(ts.n_rates) if base_levels is None else np.asarray(base_levels, float)
+        ts2 = shifted(ts, L0.detach().cpu().double().numpy(), levels.detach().cpu().double().numpy(),
+                      base)
+        g = _lib.caplet_greeks(ts2, n_paths, seed)
+        ctx.save_for_backward(torch.from_numpy(g["dP_dL0"]), torch.from_numpy(g["dP_dvol"]))
+        ctx.dev = L0.device
+        return torch.from_numpy(g["price"]).to(L0.device, L0.dtype)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        JL, JV = ctx.saved_tensors
+        go = grad_out.detach().cpu().double()
+        gL = (go @ JL).to(ctx.dev, grad_out.dtype)
+        gV = (go @ JV).to(ctx.dev, grad_out.dtype)
+        return gL, gV, None, None, None, None

@@ -244,6 +244,7 @@ int lll_plan_destroy(lll_plan *plan) {
     if (dev != plan->device) (void)hipSetDevice(plan->device);
     for (int i = 0; i < 4; ++i)
         if (plan->ev[i]) (void)hipEventDestroy(plan->ev[i]);
+    lll::greeks_free(*plan);
     free_tables(plan->d);
     if (dev != plan->device) (void)hipSetDevice(dev);
     delete plan;
@@ -550,6 +551,72 @@ int lll_batch_results(lll_batch *batch, int index, double *price_host, double *s
         return fail(LLL_EINVAL, "index %d outside 0..%d", index, (int)batch->plans.size() - 1);
     return lll_plan_results(batch->plans[index], price_host, stderr_host, mart_resid_host,
                             mart_se_host, n_itm_host, stream);
+}
+
+int lll_plan_greeks(lll_plan *plan, int64_t n_paths, uint64_t seed, void *stream) {
+    if (!plan) return fail(LLL_EINVAL, "plan is NULL");
+    if (plan->precision != LLL_FP32)
+        return fail(LLL_EUNSUPPORTED, "the adjoint runs on FP32 plans");
+    if (plan->driver != LLL_DRIVER_NIG)
+        return fail(LLL_EUNSUPPORTED, "the adjoint is implemented for the NIG driver");
+    if (n_paths < 1 || n_paths > plan->max_paths)
+        return fail(LLL_EINVAL, "n_paths=%lld outside 1..%lld", (long long)n_paths,
+                    (long long)plan->max_paths);
+    hipError_t e = lll::greeks_alloc(*plan);
+    if (e != hipSuccess) {
+        lll::greeks_free(*plan);
+        return fail(e == hipErrorOutOfMemory ? LLL_ENOMEM : LLL_EHIP,
+                    "allocating adjoint checkpoints: %s", hipGetErrorString(e));
+    }
+    hipStream_t st = as_stream(stream);
+    const bool t = plan->timing;
+    if (t) e = hipEventRecord(plan->ev[0], st);
+    if (e == hipSuccess) e = lll::launch_greeks(*plan, n_paths, seed, st);
+    if (e != hipSuccess) return hip_fail(e, "adjoint launch");
+    if (t) {
+        // whole Greeks pass timed as the path stage
+        e = hipEventRecord(plan->ev[1], st);
+        if (e == hipSuccess) e = hipEventRecord(plan->ev[2], st);
+        if (e == hipSuccess) e = hipEventRecord(plan->ev[3], st);
+        if (e != hipSuccess) return hip_fail(e, "recording timing events");
+    }
+    plan->timed = t;
+    plan->last_n_paths = n_paths;
+    plan->executed = true;
+    plan->greeks_n_paths = n_paths;
+    plan->greeks_done = true;
+    return LLL_OK;
+}
+
+int lll_plan_greeks_results(lll_plan *plan, double *price_host, double *dP_dL0_host,
+                            double *dP_dvol_host, void *stream) {
+    if (!plan) return fail(LLL_EINVAL, "plan is NULL");
+    if (!plan->greeks_done) return fail(LLL_EINVAL, "no Greeks pass has run on this plan");
+    const size_t N = plan->N;
+    std::vector<double> out(2 * N * N + N);
+    hipStream_t st = as_stream(stream);
+    hipError_t e = hipMemcpyAsync(out.data(), plan->g.out, out.size() * sizeof(double),
+                                  hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "reading Greeks");
+    if (dP_dL0_host) std::memcpy(dP_dL0_host, out.data(), N * N * sizeof(double));
+    if (dP_dvol_host) std::memcpy(dP_dvol_host, out.data() + N * N, N * N * sizeof(double));
+    if (price_host) std::memcpy(price_host, out.data() + 2 * N * N, N * sizeof(double));
+    if (!finite_all(out.data(), out.size()))
+        return fail(LLL_ENUMERIC, "non-finite Greeks");
+    return LLL_OK;
+}
+
+int lll_caplet_greeks(const lll_term_structure *ts, int64_t n_paths, uint64_t seed,
+                      double *price_host, double *dP_dL0_host, double *dP_dvol_host,
+                      void *stream) {
+    lll_plan *plan = nullptr;
+    int rc = lll_plan_create(ts, LLL_FP32, n_paths, &plan);
+    if (rc != LLL_OK) return rc;
+    rc = lll_plan_greeks(plan, n_paths, seed, stream);
+    if (rc == LLL_OK) rc = lll_plan_greeks_results(plan, price_host, dP_dL0_host, dP_dvol_host, stream);
+    lll_plan_destroy(plan);
+    return rc;
 }
 
 }  // extern "C"

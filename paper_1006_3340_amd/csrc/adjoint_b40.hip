@@ -1,0 +1,9 @@
+// adjoint_b40.hip -- adjoint kernel for the 40-slot register bucket.
+#define LLL_BUCKET_TU
+#include "adjoint_kernel.hpp"
+
+namespace lll {
+namespace adj {
+template hipError_t launch_adjoint_bucket<40>(const PathArgs<float> &, const AdjArgs &, hipStream_t);
+}  // namespace adj
+}  // namespace lll

@@ -1,0 +1,9 @@
+// adjoint_b8.hip -- adjoint kernel for the 8-slot register bucket.
+#define LLL_BUCKET_TU
+#include "adjoint_kernel.hpp"
+
+namespace lll {
+namespace adj {
+template hipError_t launch_adjoint_bucket<8>(const PathArgs<float> &, const AdjArgs &, hipStream_t);
+}  // namespace adj
+}  // namespace lll

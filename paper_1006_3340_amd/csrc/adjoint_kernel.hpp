@@ -1,0 +1,318 @@
+// adjoint_kernel.hpp -- pathwise adjoint of the caplet prices (FULL scheme, FP32).
+//
+// Caplet i's price is delta_i B(0, T_*) E[f_i], f_i = D_i (L_i(T_i) - K)^+,
+// D_i = prod_{l>i}(1 + delta_l L_l(T_i)) (paper Section 3.3, eq. (caplet)).
+// For every path the kernel differentiates f_i with respect to the initial
+// forwards L(0, T_l) and to a parallel shift of each rate's volatility curve
+// lambda(., T_l), by reverse-mode differentiation of the Euler recursion
+//     X_l <- X_l - kappa(lambda_l) dt - C_l dt + lambda_l dH,
+//     C_l = sum_q W_q E_{l,q} (P_{l,q} - 1),  P_{l,q} = prod_{m>l} (1 + ell_m E_{m,q}),
+// (eq. (LIBOR-drift-PT) with the quadrature rule), E_{l,q} = e^{lambda_l x_q} - 1,
+// ell_l = delta_l L_l / (1 + delta_l L_l), L_l = L(0, T_l) e^{X_l}.
+//
+// Rate i depends only on rates l >= i, so the sweep of caplet i carries only
+// those.  Memory: the forward pass checkpoints the live rates at every tenor
+// date (packed, N (N+1) / 2 floats per path) and the fixing of every rate;
+// each sweep recomputes one period at a time from its checkpoint into a
+// per-period scratch (steps_per_period states per path) and walks it back.
+//
+// Reverse of one step, per node q (the suffix products P by a downward pass,
+// then an upward pass with F_l = sum_{i<l} Cbar_i W E_{i,q} prod_{i<m<l} beta_m):
+//     ellbar_l += E_{l,q} P_l F_l
+//     Ebar_l    = Cbar_l W_q (P_l - 1) + ell_l P_l F_l,  lambdabar_l += x_q e^{lambda_l x_q} Ebar_l
+//     F_{l+1}   = (1 + ell_l E_{l,q}) F_l + Cbar_l W_q E_{l,q},     Cbar_l = -dt Xbar_l,
+// then Xbar_l += ellbar_l ell_l (1 - ell_l), L0bar_l += ellbar_l ell_l (1 - ell_l) / L(0, T_l),
+// lambdabar_l += Xbar_l (dH - kappa'(lambda_l) dt).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <utility>
+
+#include "lll_device.hpp"
+#include "lll_internal.hpp"
+#include "path_kernel.hpp"
+
+namespace lll {
+namespace adj {
+
+using detail::cptr;
+using detail::PathArgs;
+
+constexpr int kAdjBlock = 64;  // one wavefront per block: per-lane accumulators in LDS
+
+struct AdjArgs {
+    cptr<float> xe;        // [K][Q][nmax]  x_q e^{lambda x_q}
+    cptr<float> dkap;      // [K][nmax]     kappa'(lambda) dt
+    cptr<float> w;         // [Q]           quadrature weights
+    cptr<double> inv_L0;   // [nmax]        1 / L(0, T)
+    float *ckpt;           // [N (N+1) / 2][n_paths] live rates at the start of each period
+    float *fix;            // [N][n_paths]  X_i at its fixing
+    float *scr;            // [s][nmax][n_paths] states within one period
+    float *scr_dh;         // [s][n_paths]
+    double *gpart;         // [waves][N][2N] per-wave sums of L0bar (first N) and vbar
+    int64_t n_paths;
+};
+
+// Packed checkpoint row of rate r at the start of period m (r >= m).
+__device__ __forceinline__ int64_t ckpt_row(int N, int m, int r) {
+    return static_cast<int64_t>(m) * N - (static_cast<int64_t>(m) * (m - 1)) / 2 + (r - m);
+}
+
+__device__ __forceinline__ float increment_f(const PathArgs<float> &a, int k, int m, uint32_t p_lo,
+                                             uint32_t p_hi) {
+    const cptr<double> sc = a.steps + 4 * m;
+    const StepConsts cst{sc[0], sc[1], sc[2], sc[3]};
+    const uint4 w = philox4x32_10(make_uint4(static_cast<uint32_t>(k), p_lo, p_hi, a.stream_word),
+                                  a.key0, a.key1);
+    return static_cast<float>(increment(w, cst, a.beta, a.brownian != 0, nullptr));
+}
+
+template <int NMAX, int J0>
+__device__ __forceinline__ void store_ckpt(const PathArgs<float> &a, const AdjArgs &g, int m,
+                                           int64_t gid, bool active, const float (&X)[NMAX]) {
+    if (!active) return;
+#pragma unroll
+    for (int j = J0; j < NMAX; ++j)
+        g.ckpt[ckpt_row(a.N, m, j - a.off) * g.n_paths + gid] = X[j];
+}
+
+template <int NMAX, int... Js>
+__device__ __forceinline__ void dispatch_ckpt(std::integer_sequence<int, Js...>, int j0,
+                                              const PathArgs<float> &a, const AdjArgs &g, int m,
+                                              int64_t gid, bool active, const float (&X)[NMAX]) {
+    (void)((j0 == Js ? (store_ckpt<NMAX, Js>(a, g, m, gid, active, X), 0) : 0) + ...);
+}
+
+// Forward FULL pass with checkpoints; also the price partials.
+template <int NMAX>
+__device__ void forward(const PathArgs<float> &a, const AdjArgs &g, int64_t gid, bool active) {
+    const int64_t p = a.path_offset + gid;
+    const uint32_t p_lo = static_cast<uint32_t>(p);
+    const uint32_t p_hi = static_cast<uint32_t>(static_cast<uint64_t>(p) >> 32);
+    float X[NMAX], X1[NMAX];
+#pragma unroll
+    for (int j = 0; j < NMAX; ++j) {
+        X[j] = 0.0f;
+        X1[j] = 0.0f;
+    }
+    for (int m = 0; m < a.N; ++m) {
+        const int j0 = a.off + m;
+        dispatch_ckpt<NMAX>(std::make_integer_sequence<int, NMAX>{}, j0, a, g, m, gid, active, X);
+        for (int js = 0; js < a.s; ++js) {
+            const int k = m * a.s + js;
+            const float dH = increment_f(a, k, m, p_lo, p_hi);
+            detail::dispatch_step<float, NMAX, kFull>(std::make_integer_sequence<int, NMAX>{}, j0,
+                                                      a, k, dH, X, X1);
+        }
+        if (active) {
+            // X of the rate that fixes now (slot j0), selected from registers
+            float xf = 0.0f;
+#pragma unroll
+            for (int j = 0; j < NMAX; ++j) xf = (j == j0) ? X[j] : xf;
+            g.fix[static_cast<int64_t>(m) * g.n_paths + gid] = xf;
+        }
+        detail::dispatch_payoff<float, NMAX>(std::make_integer_sequence<int, NMAX>{}, j0, a, m,
+                                             gid, active, X);
+    }
+}
+
+// Reverse of Euler step k for the slots JC .. NMAX-1, given the state X at the
+// start of the step and Xb = adjoint of the state at its end (updated in place
+// to the adjoint at the start).  Parameter adjoints go to the LDS accumulators.
+template <int NMAX, int JC>
+__device__ __forceinline__ void reverse_step(const PathArgs<float> &a, const AdjArgs &g, int k,
+                                             float dH, const float (&X)[NMAX], float (&Xb)[NMAX],
+                                             float *__restrict__ accL0, float *__restrict__ accV) {
+    // Cbar = -dt Xbar: the factor -dt is applied once after the node loop
+    // (lb and vb below are the adjoints divided by -dt).
+    const int lane = threadIdx.x;
+    const float mdt = -a.dt[k];
+    const cptr<float> dk = g.dkap + (size_t)k * NMAX;
+    float ell[NMAX], lb[NMAX], vb[NMAX], P[NMAX];
+#pragma unroll
+    for (int j = JC; j < NMAX; ++j) {
+        ell[j] = detail::ell_of(X[j], a.cinv[j]);
+        lb[j] = 0.0f;
+        vb[j] = Xb[j] * (dH - dk[j]) / mdt;
+    }
+    cptr<float> row = a.ew + (size_t)k * kQ * NMAX * 2;
+    cptr<float> xrow = g.xe + (size_t)k * kQ * NMAX;
+#pragma unroll 1
+    for (int q = 0; q < kQ; ++q, row += NMAX * 2, xrow += NMAX) {
+        const float W = g.w[q];
+        P[NMAX - 1] = 1.0f;
+#pragma unroll
+        for (int j = NMAX - 2; j >= JC; --j)
+            P[j] = P[j + 1] * fmaf(ell[j + 1], row[2 * (j + 1)], 1.0f);
+        float F = 0.0f;
+#pragma unroll
+        for (int j = JC; j < NMAX; ++j) {
+            const float E = row[2 * j];
+            const float WE = row[2 * j + 1];
+            const float G = P[j] * F;
+            lb[j] = fmaf(E, G, lb[j]);
+            const float WR = fmaf(P[j], W, -W);  // W (P - 1)
+            const float Eb = fmaf(Xb[j], WR, ell[j] * G);
+            vb[j] = fmaf(xrow[j], Eb, vb[j]);
+            F = fmaf(fmaf(ell[j], E, 1.0f), F, Xb[j] * WE);
+        }
+    }
+#pragma unroll
+    for (int j = JC; j < NMAX; ++j) {
+        const float t = lb[j] * mdt * ell[j] * (1.0f - ell[j]);
+        Xb[j] += t;
+        accL0[j * kAdjBlock + lane] += t * static_cast<float>(g.inv_L0[j]);
+        accV[j * kAdjBlock + lane] += vb[j] * mdt;
+    }
+}
+
+// Sweep of the caplet fixing in slot JC (rate c = JC - off, period c).
+template <int NMAX, int JC>
+__device__ __forceinline__ void sweep(const PathArgs<float> &a, const AdjArgs &g, int64_t gid, bool active,
+                      float *__restrict__ accL0, float *__restrict__ accV) {
+    const int lane = threadIdx.x;
+    const int c = JC - a.off;
+    const int N = a.N;
+    const int64_t p = a.path_offset + gid;
+    const uint32_t p_lo = static_cast<uint32_t>(p);
+    const uint32_t p_hi = static_cast<uint32_t>(static_cast<uint64_t>(p) >> 32);
+    const int64_t gl = active ? gid : 0;  // lanes past the end read path 0 and contribute 0
+#pragma unroll
+    for (int j = 0; j < NMAX; ++j) {
+        accL0[j * kAdjBlock + lane] = 0.0f;
+        accV[j * kAdjBlock + lane] = 0.0f;
+    }
+    // state at the fixing date T_{c+1}
+    float X[NMAX], X1[NMAX], Xb[NMAX];
+#pragma unroll
+    for (int j = 0; j < NMAX; ++j) {
+        X[j] = 0.0f;
+        X1[j] = 0.0f;
+        Xb[j] = 0.0f;
+    }
+    X[JC] = g.fix[static_cast<int64_t>(c) * g.n_paths + gl];
+#pragma unroll
+    for (int j = JC + 1; j < NMAX; ++j)
+        X[j] = g.ckpt[ckpt_row(N, c + 1, j - a.off) * g.n_paths + gl];
+    // payoff adjoint, strike 0: f = D (L_c - K)^+
+    {
+        double D = 1.0;
+        float ellf[NMAX];
+#pragma unroll
+        for (int j = JC + 1; j < NMAX; ++j) {
+            const double L = a.L0s[j] * static_cast<double>(expf(X[j]));
+            D *= 1.0 + a.deltas[j] * L;
+            ellf[j] = static_cast<float>(a.deltas[j] * L / (1.0 + a.deltas[j] * L));
+        }
+        const double Lc = a.L0s[JC] * static_cast<double>(expf(X[JC]));
+        const double K = a.strikes[c * a.S];
+        const bool itm = active && (Lc > K);
+        const float dXc = itm ? static_cast<float>(D * Lc) : 0.0f;
+        const float dD = itm ? static_cast<float>(Lc - K) : 0.0f;
+        const float Df = static_cast<float>(D);
+        Xb[JC] = dXc;
+        accL0[JC * kAdjBlock + lane] += dXc * static_cast<float>(g.inv_L0[JC]);
+#pragma unroll
+        for (int j = JC + 1; j < NMAX; ++j) {
+            const float t = dD * Df * ellf[j];
+            Xb[j] = t;
+            accL0[j * kAdjBlock + lane] += t * static_cast<float>(g.inv_L0[j]);
+        }
+    }
+    // skip the sweep when no lane of the wavefront has a nonzero adjoint
+    bool any = false;
+#pragma unroll
+    for (int j = JC; j < NMAX; ++j) any = any || (Xb[j] != 0.0f);
+    if (__any(any)) {
+        for (int m = c; m >= 0; --m) {
+            // recompute period m from its checkpoint, keeping every step's state
+#pragma unroll
+            for (int j = JC; j < NMAX; ++j)
+                X[j] = g.ckpt[ckpt_row(N, m, j - a.off) * g.n_paths + gl];
+            for (int js = 0; js < a.s; ++js) {
+                const int k = m * a.s + js;
+                const float dH = increment_f(a, k, m, p_lo, p_hi);
+                if (active) {
+#pragma unroll
+                    for (int j = JC; j < NMAX; ++j)
+                        g.scr[(static_cast<int64_t>(js) * NMAX + j) * g.n_paths + gl] = X[j];
+                    g.scr_dh[static_cast<int64_t>(js) * g.n_paths + gl] = dH;
+                }
+                detail::step<float, NMAX, kFull, JC>(a, k, dH, X, X1);
+            }
+            for (int js = a.s - 1; js >= 0; --js) {
+                const int k = m * a.s + js;
+#pragma unroll
+                for (int j = JC; j < NMAX; ++j)
+                    X[j] = g.scr[(static_cast<int64_t>(js) * NMAX + j) * g.n_paths + gl];
+                const float dH = g.scr_dh[static_cast<int64_t>(js) * g.n_paths + gl];
+                reverse_step<NMAX, JC>(a, g, k, dH, X, Xb, accL0, accV);
+            }
+        }
+    }
+    // wavefront sums of this caplet's adjoints
+    const int64_t wave = gid / kWave;
+    double *out = g.gpart + (static_cast<int64_t>(wave) * N + c) * 2 * N;
+    for (int j = JC; j < NMAX; ++j) {
+        const double l0 = detail::wave_sum(active ? accL0[j * kAdjBlock + lane] : 0.0f);
+        const double vv = detail::wave_sum(active ? accV[j * kAdjBlock + lane] : 0.0f);
+        if (lane == 0) {
+            out[j - a.off] = l0;
+            out[N + j - a.off] = vv;
+        }
+    }
+    if (lane == 0)
+        for (int r = 0; r < c; ++r) {
+            out[r] = 0.0;
+            out[N + r] = 0.0;
+        }
+}
+
+// One launch per caplet (slot JC): each sweep is its own kernel so that its
+// register allocation covers only its own live set.
+template <int NMAX, int JC>
+__global__ void __launch_bounds__(kAdjBlock) sweep_kernel(PathArgs<float> a, AdjArgs g) {
+    __shared__ float accL0[NMAX * kAdjBlock];
+    __shared__ float accV[NMAX * kAdjBlock];
+    const int64_t gid = static_cast<int64_t>(blockIdx.x) * kAdjBlock + threadIdx.x;
+    const int64_t wave_first = gid - threadIdx.x;
+    if (wave_first >= a.n_paths) return;
+    sweep<NMAX, JC>(a, g, gid, gid < a.n_paths, accL0, accV);
+}
+
+template <int NMAX>
+__global__ void __launch_bounds__(kAdjBlock) forward_kernel(PathArgs<float> a, AdjArgs g) {
+    const int64_t gid = static_cast<int64_t>(blockIdx.x) * kAdjBlock + threadIdx.x;
+    const int64_t wave_first = gid - threadIdx.x;
+    if (wave_first >= a.n_paths) return;
+    forward<NMAX>(a, g, gid, gid < a.n_paths);
+}
+
+template <int NMAX, int JC>
+hipError_t launch_one_sweep(dim3 grid, const PathArgs<float> &a, const AdjArgs &g, hipStream_t st) {
+    hipLaunchKernelGGL((sweep_kernel<NMAX, JC>), grid, dim3(kAdjBlock), 0, st, a, g);
+    return hipGetLastError();
+}
+
+template <int NMAX, int... Js>
+hipError_t launch_sweep(std::integer_sequence<int, Js...>, int jc, dim3 grid,
+                        const PathArgs<float> &a, const AdjArgs &g, hipStream_t st) {
+    hipError_t e = hipErrorInvalidValue;
+    (void)((jc == Js ? (e = launch_one_sweep<NMAX, Js>(grid, a, g, st), 0) : 0) + ...);
+    return e;
+}
+
+// Forward pass with checkpoints, then one sweep launch per caplet.
+template <int NMAX>
+hipError_t launch_adjoint_bucket(const PathArgs<float> &a, const AdjArgs &g, hipStream_t st) {
+    const dim3 grid(static_cast<unsigned>((a.n_paths + kAdjBlock - 1) / kAdjBlock));
+    hipLaunchKernelGGL(forward_kernel<NMAX>, grid, dim3(kAdjBlock), 0, st, a, g);
+    hipError_t e = hipGetLastError();
+    for (int c = 0; c < a.N && e == hipSuccess; ++c)
+        e = launch_sweep<NMAX>(std::make_integer_sequence<int, NMAX>{}, a.off + c, grid, a, g, st);
+    return e;
+}
+
+}  // namespace adj
+}  // namespace lll

@@ -46,6 +46,15 @@ struct DeviceTables {
 
 }  // namespace lll
 
+namespace lll {
+struct GreeksBuffers {
+    float *xe = nullptr, *dkap = nullptr, *w32 = nullptr;
+    double *inv_L0 = nullptr;
+    float *ckpt = nullptr, *fix = nullptr, *scr = nullptr, *scr_dh = nullptr;
+    double *gpart = nullptr, *gchunks = nullptr, *gsums = nullptr, *out = nullptr;
+};
+}  // namespace lll
+
 struct lll_plan {
     int N = 0, s = 0, S = 0, K = 0, driver = 0, precision = 0, nmax = 0, off = 0;
     uint32_t struct_id = 0;
@@ -54,7 +63,9 @@ struct lll_plan {
     int device = 0;
     std::vector<double> tenor, delta, L0, vol, strikes;
     lll::DeviceTables d;
-    int64_t last_n_paths = 0;
+    lll::GreeksBuffers g;
+    int64_t last_n_paths = 0, greeks_n_paths = 0;
+    bool greeks_done = false;
     bool executed = false;
     bool timing = false, timed = false;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -74,6 +85,11 @@ struct lll_batch {
 namespace lll {
 
 constexpr int kStatBase = 3;  // NSTAT = 3 S + 2
+
+// adjoint.hip
+hipError_t greeks_alloc(lll_plan &p);
+void greeks_free(lll_plan &p);
+hipError_t launch_greeks(const lll_plan &p, int64_t n_paths, uint64_t seed, hipStream_t st);
 
 // batched.hip
 size_t batch_item_bytes();

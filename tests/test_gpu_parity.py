@@ -340,3 +340,121 @@ def test_batched_full_size_vs_single(gpu_lib):
                 plan.execute(FULL, n, seed=1)
                 ref = plan.results()
             assert np.allclose(b.results(i)["price"], ref["price"], rtol=1e-6, atol=1e-300), i
+
+
+# ---------------------------------------------------------------------------
+# Pathwise adjoint (caplet deltas and vegas)
+# ---------------------------------------------------------------------------
+
+def _greeks_structure(N=8, levels=None, L0=None):
+    if L0 is None:
+        L0 = 0.03 + 0.001 * np.arange(1, N + 1)
+    if levels is None:
+        levels = np.full(N, 0.12)
+    return workloads.make_structure(N, 0.25, L0, 10, workloads.exp_decay_vol(levels=levels), [1.0],
+                                    B0_T1=1.0 / (1.0 + 0.25 * 0.031))
+
+
+def _oracle_fd(oracle_mod, N, n, h):
+    """Central differences of the FP64 oracle's FULL caplet prices under common
+    random numbers: bumps of L(0,T_l) and of the vol level v_l (B(0,T_1) held)."""
+    L0 = 0.03 + 0.001 * np.arange(1, N + 1)
+    lv = np.full(N, 0.12)
+    JL = np.zeros((N, N)); JV = np.zeros((N, N))
+    for l in range(N):
+        for J, bump in ((JL, "L"), (JV, "v")):
+            prices = []
+            for sgn in (+1, -1):
+                L = L0.copy(); v = lv.copy()
+                (L if bump == "L" else v)[l] += sgn * h
+                ts = _greeks_structure(N, levels=v, L0=L)
+                prices.append(oracle_mod.Oracle(ts, seed=1).price(FULL, n)["price"][:, 0])
+            J[:, l] = (prices[0] - prices[1]) / (2 * h)
+    return JL, JV
+
+
+@pytest.mark.parametrize("h,rtol", [(1e-6, 2e-3), (1e-4, 3e-2)])
+def test_greeks_match_oracle_finite_differences(gpu_lib, oracle_mod, h, rtol):
+    N, n = 8, 2000
+    ts = _greeks_structure(N)
+    with gpu_lib.Plan(ts, precision=0, max_paths=n) as plan:
+        plan.greeks(n, seed=1)
+        g = plan.greeks_results()
+    JL, JV = _oracle_fd(oracle_mod, N, n, h)
+    for got, ref in ((g["dP_dL0"], JL), (g["dP_dvol"], JV)):
+        scale = np.max(np.abs(ref), axis=1, keepdims=True)
+        assert np.all(np.abs(got - ref) <= rtol * np.abs(ref) + rtol * 1e-2 * scale), (got, ref)
+    ref_price = oracle_mod.Oracle(ts, seed=1).price(FULL, n)["price"][:, 0]
+    assert np.allclose(g["price"], ref_price, rtol=1e-4)
+
+
+def test_greeks_full_size_structure_and_fourier(gpu_lib):
+    """N=40 quarterly, 2^20 paths: exact zero pattern, the discount-factor term
+    below the diagonal, prices equal to the plain FULL pass, the terminal
+    caplet's delta and vega against the Fourier price's derivatives, and a few
+    entries against common-random-number finite differences on the GPU."""
+    from test_oracle_pricing import lewis_terminal_caplet
+    ts = workloads.adjoint_greeks()
+    N, n = ts.n_rates, 1 << 20
+    with gpu_lib.Plan(ts, precision=0, max_paths=n) as plan:
+        plan.greeks(n, seed=1)
+        g = plan.greeks_results()
+        plan.execute(FULL, n, seed=1)
+        plain = plan.results()["price"][:, 0]
+    P, JL, JV = g["price"], g["dP_dL0"], g["dP_dvol"]
+    assert np.allclose(P, plain, rtol=1e-12, atol=0)
+    disc = -P[:, None] * (ts.delta / (1.0 + ts.delta * ts.L0))[None, :]
+    for c in range(N):
+        assert np.all(JV[c, :c] == 0.0)
+        assert np.allclose(JL[c, :c], disc[c, :c], rtol=1e-12, atol=0)
+    # terminal caplet: X_N is a sum of independent NIG increments (no drift coupling)
+    B0T = ts.B0_T1 / np.prod(1.0 + ts.delta * ts.L0)
+
+    def terminal_price(L0N, shift):
+        t2 = ts.copy(L0=np.concatenate([ts.L0[:-1], [L0N]]), vol=ts.vol.copy())
+        t2.vol[:, N - 1] += shift
+        t2.strikes = ts.strikes.copy()
+        B = ts.B0_T1 / np.prod(1.0 + t2.delta * t2.L0)
+        return t2.delta[N - 1] * B * lewis_terminal_caplet(t2)[0]
+    hL, hv = 1e-6, 1e-6
+    dL_ref = (terminal_price(ts.L0[-1] + hL, 0) - terminal_price(ts.L0[-1] - hL, 0)) / (2 * hL)
+    dv_ref = (terminal_price(ts.L0[-1], hv) - terminal_price(ts.L0[-1], -hv)) / (2 * hv)
+    assert abs(JL[N - 1, N - 1] / dL_ref - 1.0) < 1e-2, (JL[N - 1, N - 1], dL_ref)
+    assert abs(JV[N - 1, N - 1] / dv_ref - 1.0) < 1e-2, (JV[N - 1, N - 1], dv_ref)
+    # common-random-number central differences on the GPU for a few entries
+    h = 1e-4
+    from paper_1006_3340_amd.autograd import shifted
+    for l in (0, 20, 39):
+        for kind in ("L", "v"):
+            vals = []
+            for sgn in (+1, -1):
+                dL0 = np.zeros(N); dv = np.zeros(N)
+                (dL0 if kind == "L" else dv)[l] = sgn * h
+                t2 = shifted(ts, ts.L0 + dL0, dv, np.zeros(N))
+                with gpu_lib.Plan(t2, precision=0, max_paths=n) as p2:
+                    p2.execute(FULL, n, seed=1)
+                    vals.append(p2.results()["price"][:, 0])
+            fd = (vals[0] - vals[1]) / (2 * h)
+            J = JL if kind == "L" else JV
+            for c in (0, l // 2, l):
+                assert abs(J[c, l] - fd[c]) <= 3e-2 * abs(fd[c]) + 1e-3 * np.max(np.abs(fd)), \
+                    (kind, l, c, J[c, l], fd[c])
+
+
+def test_autograd_function(gpu_lib):
+    import torch
+    from paper_1006_3340_amd.autograd import CapletPrice
+    N = 8
+    ts = _greeks_structure(N)
+    base = np.full(N, 0.12)
+    L0 = torch.tensor(ts.L0, dtype=torch.float64, requires_grad=True)
+    lv = torch.tensor(base, dtype=torch.float64, requires_grad=True)
+    w = torch.linspace(1.0, 2.0, N, dtype=torch.float64)
+    P = CapletPrice.apply(L0, lv, ts, 4096, 1, base)
+    (P * w).sum().backward()
+    with gpu_lib.Plan(ts, precision=0, max_paths=4096) as plan:
+        plan.greeks(4096, seed=1)
+        g = plan.greeks_results()
+    assert np.allclose(P.detach().numpy(), g["price"], rtol=0, atol=0)
+    assert np.allclose(L0.grad.numpy(), w.numpy() @ g["dP_dL0"], rtol=1e-12)
+    assert np.allclose(lv.grad.numpy(), w.numpy() @ g["dP_dvol"], rtol=1e-12)
