@@ -357,9 +357,11 @@ def _greeks_structure(N=8, levels=None, L0=None):
 
 def _oracle_fd(oracle_mod, N, n, h):
     """Central differences of the FP64 oracle's FULL caplet prices under common
-    random numbers: bumps of L(0,T_l) and of the vol level v_l (B(0,T_1) held)."""
+    random numbers: bumps of L(0,T_l) and of the vol level v_l (B(0,T_1) and
+    the absolute strikes held)."""
     L0 = 0.03 + 0.001 * np.arange(1, N + 1)
     lv = np.full(N, 0.12)
+    K = _greeks_structure(N).strikes
     JL = np.zeros((N, N)); JV = np.zeros((N, N))
     for l in range(N):
         for J, bump in ((JL, "L"), (JV, "v")):
@@ -367,7 +369,7 @@ def _oracle_fd(oracle_mod, N, n, h):
             for sgn in (+1, -1):
                 L = L0.copy(); v = lv.copy()
                 (L if bump == "L" else v)[l] += sgn * h
-                ts = _greeks_structure(N, levels=v, L0=L)
+                ts = _greeks_structure(N, levels=v, L0=L).copy(strikes=K)
                 prices.append(oracle_mod.Oracle(ts, seed=1).price(FULL, n)["price"][:, 0])
             J[:, l] = (prices[0] - prices[1]) / (2 * h)
     return JL, JV
