@@ -86,6 +86,38 @@ def cpu_baseline(ts, n_sample: int, schemes) -> dict:
                       f"({'+'.join(schemes)}) of the same workload, {dt:.1f} s"}
 
 
+def adjoint_flops_per_path(ts) -> int:
+    """Algorithmic FP32 flops of the Greeks pass per path: the FULL forward pass,
+    then for every caplet c (n = N - c rates carried) and every step up to its
+    fixing, one recomputed FULL step plus the reverse step (18 flops per
+    (rate, node): suffix product 3, F recursion 5, the adjoints of ell and E 10)."""
+    N, s = ts.n_rates, ts.steps_per_period
+    total = flops_per_path(ts, "full")
+    for c in range(N):
+        n = N - c
+        per_step = flops_per_path_step("full", n) + 18 * Q * n + 10 * n
+        total += (c + 1) * s * per_step
+    return total
+
+
+def bench_adjoint(lll, stream, n: int = 1 << 20) -> dict:
+    """Pathwise Greeks of 40 ATM caplets (N=40 quarterly, 2^20 paths, FP32)."""
+    ts = workloads.adjoint_greeks()
+    with lll.Plan(ts, precision=lll.FP32, max_paths=n) as plan:
+        plan.set_timing(True)
+        plan.greeks(n, seed=1, stream=stream)   # warmup (allocates checkpoints)
+        plan.greeks(n, seed=1, stream=stream)
+        ms = plan.timing()["paths"]
+        g = plan.greeks_results(stream)
+    if not np.all(np.isfinite(g["dP_dL0"])):
+        raise RuntimeError("non-finite Greeks")
+    fl = adjoint_flops_per_path(ts) * n
+    t = ms / 1e3
+    return {"workload": ts.name, "n_paths": n, "ms": ms,
+            "forward_path_steps_per_s": n * ts.n_steps / t,
+            "fp32_tflops": fl / t / 1e12, "frac_fp32_peak": fl / t / PEAK_FP32}
+
+
 def bench_batched(lll, stream, schemes, n_each: int = 1 << 18, reps: int = 2) -> dict:
     """64 independent structures in one persistent launch: kernel time (HIP events
     recorded by the library), path-steps/s and FP32 fraction of peak."""
@@ -118,6 +150,8 @@ def main(argv=None) -> int:
                     help="paths of the oracle timing sample (0 skips it)")
     ap.add_argument("--batched", type=int, default=1,
                     help="also time the 64-structure persistent launch (2^18 paths each)")
+    ap.add_argument("--adjoint", type=int, default=1,
+                    help="also time the pathwise Greeks pass (N=40, 2^20 paths)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (a kernel of "
                          "known traffic for calibrating HBM counters)")
@@ -214,6 +248,8 @@ def main(argv=None) -> int:
     }
     if args.batched:
         out["batched"] = bench_batched(lll, stream, schemes)
+    if args.adjoint:
+        out["adjoint"] = bench_adjoint(lll, stream)
     if args.cpu_sample > 0:
         out["cpu_baseline"] = cpu_baseline(ts, args.cpu_sample, schemes)
     plan.close()

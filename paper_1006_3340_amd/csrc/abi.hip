@@ -570,13 +570,13 @@ int lll_plan_greeks(lll_plan *plan, int64_t n_paths, uint64_t seed, void *stream
     }
     hipStream_t st = as_stream(stream);
     const bool t = plan->timing;
+    // the whole Greeks pass is timed as the path stage (events 1 -> 2)
     if (t) e = hipEventRecord(plan->ev[0], st);
+    if (t && e == hipSuccess) e = hipEventRecord(plan->ev[1], st);
     if (e == hipSuccess) e = lll::launch_greeks(*plan, n_paths, seed, st);
     if (e != hipSuccess) return hip_fail(e, "adjoint launch");
     if (t) {
-        // whole Greeks pass timed as the path stage
-        e = hipEventRecord(plan->ev[1], st);
-        if (e == hipSuccess) e = hipEventRecord(plan->ev[2], st);
+        e = hipEventRecord(plan->ev[2], st);
         if (e == hipSuccess) e = hipEventRecord(plan->ev[3], st);
         if (e != hipSuccess) return hip_fail(e, "recording timing events");
     }
