@@ -171,6 +171,78 @@ int lll_caplet_greeks(const lll_term_structure *ts, int64_t n_paths, uint64_t se
                       double *price_host, double *dP_dL0_host, double *dP_dvol_host,
                       void *stream);
 
+/* ---- learned drift surrogate ---- */
+
+/* A small network that corrects the first-order drift expansion of paper
+ * Section 3.2 (eq. (drifta)) towards the 64-node quadrature coupling:
+ *   C_i = C'_i + sigma * net(t_k / T_N, X_{l>i}, onehot(i)),
+ * C'_i = sum_{l>i} ell_l [kappa(lambda_i + lambda_l) - kappa(lambda_i) - kappa(lambda_l)],
+ * 96 inputs (81 used: t, the 40 later-rate log-rate states X_l = log L_l/L_l(0),
+ * the 40-wide rate one-hot), 3 hidden layers of 64 with tanh-form GELU, one
+ * output; BF16 matrix-core operands with FP32 accumulation and FP32 master
+ * weights.  Parameter vector (LLL_MLP_PARAMS floats): W1[64][96] b1[64]
+ * W2[64][64] b2[64] W3[64][64] b3[64] w4[64] b4.  The surrogate serves plans
+ * of 33..40 rates (the 40-slot register bucket), FP32, NIG driver. */
+#define LLL_MLP_PARAMS 14593
+#define LLL_MLP_INPUTS 96
+typedef struct lll_mlp lll_mlp;
+
+/* Allocate a network on the current device with Glorot-uniform weights drawn
+ * from Philox (key = seed, counter word 3 = tag 2) and zero biases. */
+int lll_mlp_create(uint64_t seed, lll_mlp **mlp_out);
+int lll_mlp_destroy(lll_mlp *mlp);
+
+/* Copy the FP32 parameter vector to get_host and/or replace it from set_host
+ * (either may be NULL; setting resets the optimiser state).  Synchronous. */
+int lll_mlp_params(lll_mlp *mlp, float *get_host, const float *set_host);
+
+/* Training pairs from the plan's term structure: n_paths FULL paths on their
+ * own random stream (counter word 3 = struct_id | 1 << 24) record their state
+ * at `records` staggered steps; every recorded state yields one pair per live
+ * rate i with BF16 features and the FP64 label C_i - C'_i (quadrature coupling
+ * minus first-order expansion), stored in FP32.  Also computes the per-rate
+ * state range (the trust box of the fallback) and the label scale sigma (root
+ * mean square).  Synchronous; *n_pairs_out receives the number of pairs. */
+int lll_mlp_generate(lll_mlp *mlp, lll_plan *plan, int64_t n_paths, int records, uint64_t seed,
+                     int64_t *n_pairs_out, void *stream);
+
+/* info_host[81]: box minimum per rate [40], box maximum per rate [40], sigma. */
+int lll_mlp_info(lll_mlp *mlp, float *info_host, int64_t *n_pairs);
+
+/* For pairs[n]: the recorded state [n][40] (FP32, by rate), its step, the
+ * pair's rate, its label and its features [n][96] (BF16 values as FP32).
+ * Any output may be NULL. */
+int lll_mlp_pairs(lll_mlp *mlp, const int64_t *pairs, int64_t n, float *state_host, int *k_host,
+                  int *rate_host, float *label_host, float *feat_host);
+
+/* n_steps Adam steps (beta 0.9 / 0.999, cosine decay of lr to lr / 100) on
+ * minibatches of `batch` pairs drawn with replacement (Philox key seed, tag 2),
+ * loss = mean squared error of the labels divided by sigma.  loss_host[n_steps]
+ * (may be NULL) receives the minibatch losses.  Synchronous. */
+int lll_mlp_train(lll_mlp *mlp, int n_steps, int batch, float lr, uint64_t seed, float *loss_host,
+                  void *stream);
+
+/* Forward pass on n host feature rows [n][96] (rounded to BF16 on the device):
+ * outputs y_host[n]; with targets (target_host[n]) also the gradient of
+ * loss = sum (y - target)^2 / (2 n) with respect to the parameter vector
+ * (grad_host[LLL_MLP_PARAMS]) and the loss.  Synchronous. */
+int lll_mlp_eval(lll_mlp *mlp, const float *feat_host, const float *target_host, int64_t n,
+                 float *y_host, float *grad_host, float *loss_host, void *stream);
+
+/* Pricing pass (as lll_plan_execute, FULL-scheme Euler steps) whose coupling
+ * is C'_i + sigma * net (use_net = 1) or the first-order expansion C'_i alone
+ * (use_net = 0, mlp may be NULL).  A path whose state of a later rate leaves
+ * the training range takes the quadrature coupling for that rate (fallback);
+ * every judge_stride-th wavefront (0: none) also evaluates the quadrature at
+ * every step and records the surrogate's errors.  Asynchronous. */
+int lll_plan_execute_mlp(lll_plan *plan, const lll_mlp *mlp, int use_net, int64_t n_paths,
+                         uint64_t seed, int judge_stride, double *path_fix_dev, void *stream);
+
+/* Statistics of the last surrogate pass, stats_host[8]: rate-steps evaluated,
+ * fallbacks taken, judged rate-steps, sum |C - C_quad| over judged rate-steps,
+ * sum |C_quad|, max |C - C_quad| / |C_quad|, 0, 0. */
+int lll_plan_mlp_stats(lll_plan *plan, double *stats_host, void *stream);
+
 /* ---- many term structures in one persistent launch ---- */
 
 /* Opaque batch of n_ts independent term structures (FP32 path arithmetic).

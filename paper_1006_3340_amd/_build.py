@@ -11,7 +11,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblll.so")
-SOURCES = ["abi.hip", "precompute.hip", "paths.hip", "batched.hip", "adjoint.hip"] + sorted(
+SOURCES = ["abi.hip", "precompute.hip", "paths.hip", "batched.hip", "adjoint.hip",
+           "mlp_train.hip", "mlp_path.hip", "mlp_host.hip"] + sorted(
     f for f in os.listdir(CSRC) if f.startswith(("bucket_", "adjoint_b")) and f.endswith(".hip"))
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -31,7 +32,7 @@ PATH_FLAGS = ["-mllvm", "-disable-machine-licm"]
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    extra = PATH_FLAGS if src.startswith(("bucket_", "batched", "adjoint")) else []
+    extra = PATH_FLAGS if src.startswith(("bucket_", "batched", "adjoint", "mlp_")) else []
     cmd = [HIPCC, *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

@@ -28,7 +28,11 @@ EXPORTS = ["lll_version", "lll_last_error", "lll_plan_create", "lll_plan_execute
            "lll_price_caplets", "lll_philox", "lll_plan_increments", "lll_plan_tables",
            "lll_plan_drift", "lll_plan_set_timing", "lll_plan_timing", "lll_batch_create",
            "lll_batch_execute", "lll_batch_results", "lll_batch_set_timing", "lll_batch_timing",
-           "lll_batch_destroy", "lll_plan_greeks", "lll_plan_greeks_results", "lll_caplet_greeks"]
+           "lll_batch_destroy", "lll_plan_greeks", "lll_plan_greeks_results", "lll_caplet_greeks",
+           "lll_mlp_create", "lll_mlp_destroy", "lll_mlp_params", "lll_mlp_generate",
+           "lll_mlp_info", "lll_mlp_pairs", "lll_mlp_train", "lll_mlp_eval",
+           "lll_plan_execute_mlp", "lll_plan_mlp_stats"]
+MLP_PARAMS, MLP_INPUTS = 14593, 96
 
 
 class LLLError(RuntimeError):
@@ -86,6 +90,19 @@ def load():
     lib.lll_plan_increments.argtypes = [vp, i32, i64, i64, u64, dp, dp, vp]
     lib.lll_plan_tables.argtypes = [vp, dp, dp, dp, dp, dp, vp]
     lib.lll_plan_drift.argtypes = [vp, i32, dp, i64, dp, vp]
+    fp = ctypes.POINTER(ctypes.c_float)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    i32p = ctypes.POINTER(ctypes.c_int)
+    lib.lll_mlp_create.argtypes = [u64, ctypes.POINTER(vp)]
+    lib.lll_mlp_destroy.argtypes = [vp]
+    lib.lll_mlp_params.argtypes = [vp, fp, fp]
+    lib.lll_mlp_generate.argtypes = [vp, vp, i64, i32, u64, i64p, vp]
+    lib.lll_mlp_info.argtypes = [vp, fp, i64p]
+    lib.lll_mlp_pairs.argtypes = [vp, i64p, i64, fp, i32p, i32p, fp, fp]
+    lib.lll_mlp_train.argtypes = [vp, i32, i32, ctypes.c_float, u64, fp, vp]
+    lib.lll_mlp_eval.argtypes = [vp, fp, fp, i64, fp, fp, fp, vp]
+    lib.lll_plan_execute_mlp.argtypes = [vp, vp, i32, i64, u64, i32, vp, vp]
+    lib.lll_plan_mlp_stats.argtypes = [vp, dp, vp]
     lib.lll_plan_greeks.argtypes = [vp, i64, u64, vp]
     lib.lll_plan_greeks_results.argtypes = [vp, dp, dp, dp, vp]
     lib.lll_caplet_greeks.argtypes = [ctypes.POINTER(TermStructureC), i64, u64, dp, dp, dp, vp]
@@ -197,6 +214,21 @@ class Plan:
         ms = (ctypes.c_float * 3)()
         _check(self.lib.lll_plan_timing(self.h, ms))
         return {"precompute": ms[0], "paths": ms[1], "reduce": ms[2]}
+
+    def execute_mlp(self, mlp, use_net: bool, n_paths: int, seed: int = 1, judge_stride: int = 0,
+                    path_fix=None, stream=None):
+        """Pricing pass with the surrogate drift (use_net) or the first-order expansion alone."""
+        _check(self.lib.lll_plan_execute_mlp(self.h, mlp.h if mlp is not None else None,
+                                             1 if use_net else 0, int(n_paths), int(seed),
+                                             int(judge_stride), device_ptr(path_fix),
+                                             stream_handle(stream)))
+        self.n_paths = int(n_paths)
+
+    def mlp_stats(self, stream=None) -> dict:
+        out = np.zeros(8)
+        _check(self.lib.lll_plan_mlp_stats(self.h, _dp(out), stream_handle(stream)))
+        return {"rate_steps": out[0], "fallbacks": out[1], "judged": out[2],
+                "judge_abs_err": out[3], "judge_abs_quad": out[4], "judge_max_rel": out[5]}
 
     def greeks(self, n_paths: int, seed: int = 1, stream=None):
         """Enqueue the FULL pricing pass with the pathwise adjoint (lll_plan_greeks)."""
@@ -314,6 +346,94 @@ def price_caplets(ts, n_paths: int, scheme: int = FULL, seed: int = 1, precision
                                  int(precision), _dp(price), _dp(se), _dp(mart),
                                  stream_handle(stream)))
     return {"price": price, "stderr": se, "mart_resid": mart}
+
+
+def _fp(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+class Mlp:
+    """lll_mlp: the drift surrogate (weights, training data, optimiser state)."""
+
+    def __init__(self, seed: int = 1):
+        self.lib = load()
+        h = ctypes.c_void_p()
+        _check(self.lib.lll_mlp_create(int(seed), ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.lll_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def params(self) -> np.ndarray:
+        out = np.zeros(MLP_PARAMS, dtype=np.float32)
+        _check(self.lib.lll_mlp_params(self.h, _fp(out), None))
+        return out
+
+    def set_params(self, p: np.ndarray):
+        p = np.ascontiguousarray(np.asarray(p, dtype=np.float32))
+        assert p.shape == (MLP_PARAMS,)
+        _check(self.lib.lll_mlp_params(self.h, None, _fp(p)))
+
+    def generate(self, plan: "Plan", n_paths: int, records: int, seed: int = 1, stream=None) -> int:
+        n = ctypes.c_int64()
+        _check(self.lib.lll_mlp_generate(self.h, plan.h, int(n_paths), int(records), int(seed),
+                                         ctypes.byref(n), stream_handle(stream)))
+        return n.value
+
+    def info(self) -> dict:
+        out = np.zeros(81, dtype=np.float32)
+        n = ctypes.c_int64()
+        _check(self.lib.lll_mlp_info(self.h, _fp(out), ctypes.byref(n)))
+        return {"lo": out[:40].copy(), "hi": out[40:80].copy(), "sigma": float(out[80]),
+                "n_pairs": n.value}
+
+    def pairs(self, idx) -> dict:
+        idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int64))
+        n = len(idx)
+        st = np.zeros((n, 40), dtype=np.float32)
+        k = np.zeros(n, dtype=np.int32); r = np.zeros(n, dtype=np.int32)
+        lab = np.zeros(n, dtype=np.float32); feat = np.zeros((n, MLP_INPUTS), dtype=np.float32)
+        i32p = ctypes.POINTER(ctypes.c_int)
+        _check(self.lib.lll_mlp_pairs(self.h, idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                      n, _fp(st), k.ctypes.data_as(i32p), r.ctypes.data_as(i32p),
+                                      _fp(lab), _fp(feat)))
+        return {"state": st, "k": k, "rate": r, "label": lab, "feat": feat}
+
+    def train(self, n_steps: int, batch: int = 16384, lr: float = 2e-3, seed: int = 1,
+              stream=None) -> np.ndarray:
+        loss = np.zeros(n_steps, dtype=np.float32)
+        _check(self.lib.lll_mlp_train(self.h, int(n_steps), int(batch), ctypes.c_float(lr),
+                                      int(seed), _fp(loss), stream_handle(stream)))
+        return loss
+
+    def eval(self, feat: np.ndarray, target: Optional[np.ndarray] = None, stream=None) -> dict:
+        feat = np.ascontiguousarray(np.asarray(feat, dtype=np.float32))
+        n = feat.shape[0]
+        y = np.zeros(n, dtype=np.float32)
+        out = {"y": y}
+        if target is not None:
+            target = np.ascontiguousarray(np.asarray(target, dtype=np.float32))
+            g = np.zeros(MLP_PARAMS, dtype=np.float32); loss = np.zeros(1, dtype=np.float32)
+            _check(self.lib.lll_mlp_eval(self.h, _fp(feat), _fp(target), n, _fp(y), _fp(g),
+                                         _fp(loss), stream_handle(stream)))
+            out.update(grad=g, loss=float(loss[0]))
+        else:
+            _check(self.lib.lll_mlp_eval(self.h, _fp(feat), None, n, _fp(y), None, None,
+                                         stream_handle(stream)))
+        return out
 
 
 def caplet_greeks(ts, n_paths: int, seed: int = 1, stream=None) -> dict:

@@ -12,7 +12,7 @@
 #include "lll.h"
 #include "lll_internal.hpp"
 
-namespace {
+namespace lll {
 
 thread_local std::string g_last_error;
 
@@ -29,6 +29,14 @@ int fail(int code, const char *fmt, ...) {
 int hip_fail(hipError_t e, const char *what) {
     return fail(LLL_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
+
+}  // namespace lll
+
+namespace {
+
+using lll::fail;
+using lll::g_last_error;
+using lll::hip_fail;
 
 bool finite_all(const double *a, size_t n) {
     for (size_t i = 0; i < n; ++i)
@@ -245,6 +253,7 @@ int lll_plan_destroy(lll_plan *plan) {
     for (int i = 0; i < 4; ++i)
         if (plan->ev[i]) (void)hipEventDestroy(plan->ev[i]);
     lll::greeks_free(*plan);
+    lll::mlp_plan_free(*plan);
     free_tables(plan->d);
     if (dev != plan->device) (void)hipSetDevice(dev);
     delete plan;

@@ -47,6 +47,12 @@ struct DeviceTables {
 }  // namespace lll
 
 namespace lll {
+struct MlpBuffers {
+    float *K2 = nullptr, *tnorm = nullptr, *W1T = nullptr, *open_box = nullptr;
+    void *zero_params = nullptr;  // zero FP32 + BF16 parameter vectors (first-order runs)
+    double *stats = nullptr;
+    int64_t stat_waves = 0;
+};
 struct GreeksBuffers {
     float *xe = nullptr, *dkap = nullptr, *w32 = nullptr;
     double *inv_L0 = nullptr;
@@ -64,7 +70,9 @@ struct lll_plan {
     std::vector<double> tenor, delta, L0, vol, strikes;
     lll::DeviceTables d;
     lll::GreeksBuffers g;
+    lll::MlpBuffers mb;
     int64_t last_n_paths = 0, greeks_n_paths = 0;
+    bool mlp_done = false;
     bool greeks_done = false;
     bool executed = false;
     bool timing = false, timed = false;
@@ -86,10 +94,17 @@ namespace lll {
 
 constexpr int kStatBase = 3;  // NSTAT = 3 S + 2
 
+// abi.hip: thread-local error text of the C ABI
+int fail(int code, const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+
 // adjoint.hip
 hipError_t greeks_alloc(lll_plan &p);
 void greeks_free(lll_plan &p);
 hipError_t launch_greeks(const lll_plan &p, int64_t n_paths, uint64_t seed, hipStream_t st);
+
+// mlp_host.hip
+void mlp_plan_free(lll_plan &p);
 
 // batched.hip
 size_t batch_item_bytes();

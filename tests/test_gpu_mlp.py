@@ -1,0 +1,152 @@
+"""The learned drift surrogate on the GPU: its BF16-MFMA forward and backward
+kernels against the FP64 reference (oracle/mlp.py, with the device's BF16
+operand rounding reproduced), its training labels against the FP64 oracle's
+drift, training progress, and what the trained network gains over the
+first-order expansion it corrects, judged against the quadrature drift.
+
+Tolerances: the device accumulates BF16 products in FP32 and evaluates the
+activation with hardware exp / reciprocal (relative error ~1e-6); the
+reference accumulates exactly.  An activation that lands within that error of
+a BF16 rounding boundary rounds the other way (one BF16 ulp, 2^-8 relative),
+so outputs agree to ~1e-3 of their scale and gradients, which sum many such
+products, to ~1e-2 in norm.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import mlp as M
+
+pytestmark = pytest.mark.gpu
+
+FULL, PICARD = 0, 1
+
+
+def _features(rng, n, N=40):
+    f = np.zeros((n, 96), dtype=np.float32)
+    i = rng.integers(0, N, n)
+    f[:, 0] = rng.uniform(0, 1, n)
+    for j in range(n):
+        f[j, 1 + i[j] + 1:1 + N] = rng.normal(0, 0.3, N - i[j] - 1)
+        f[j, 41 + i[j]] = 1.0
+    return f
+
+
+def test_forward_and_gradients_match_reference(gpu_lib):
+    rng = np.random.default_rng(1)
+    with gpu_lib.Mlp(seed=7) as net:
+        p = net.params().astype(np.float64)
+        # non-zero biases exercise every parameter
+        p[6144:6208] = rng.normal(0, 0.1, 64)
+        p[10304:10368] = rng.normal(0, 0.1, 64)
+        p[14464:14528] = rng.normal(0, 0.1, 64)
+        p[14592] = 0.05
+        net.set_params(p.astype(np.float32))
+        p = net.params().astype(np.float64)
+        X = _features(rng, 1000)
+        t = rng.normal(0, 1, 1000).astype(np.float32)
+        out = net.eval(X, t)
+    y_ref, _ = M.forward(p, X, bf=True)
+    scale = np.sqrt(np.mean(y_ref ** 2))
+    assert np.max(np.abs(out["y"] - y_ref)) <= 2e-3 * scale + 1e-6
+    loss_ref, g_ref = M.loss_and_grad(p, X, t, bf=True)
+    assert abs(out["loss"] - loss_ref) <= 1e-3 * loss_ref
+    offs = [0, 6144, 6208, 10304, 10368, 14464, 14528, 14592, 14593]
+    for a, b in zip(offs[:-1], offs[1:]):
+        ga, gr = out["grad"][a:b], g_ref[a:b]
+        err = np.linalg.norm(ga - gr) / max(np.linalg.norm(gr), 1e-30)
+        assert err < 1e-2, (a, b, err)
+    # without the BF16 rounding the reference differs by more than the device does
+    y64, _ = M.forward(p, X, bf=False)
+    assert np.max(np.abs(out["y"] - y_ref)) < np.max(np.abs(y64 - y_ref)) + 1e-6
+
+
+def _kappa(u, ts):
+    g = math.sqrt(ts.alpha ** 2 - ts.beta ** 2)
+    mu = -ts.delta_nig * ts.beta / g
+    return mu * u + ts.delta_nig * (g - np.sqrt(ts.alpha ** 2 - (ts.beta + u) ** 2))
+
+
+def test_training_labels_match_oracle(gpu_lib, oracle_mod):
+    ts = workloads.learned_drift()
+    o = oracle_mod.Oracle(ts)
+    with gpu_lib.Plan(ts, precision=0, max_paths=1024) as plan, gpu_lib.Mlp(seed=1) as net:
+        n_pairs = net.generate(plan, 256, 8, seed=5)
+        info = net.info()
+        assert n_pairs == info["n_pairs"] > 0 and info["sigma"] > 0
+        rng = np.random.default_rng(3)
+        d = net.pairs(rng.choice(n_pairs, 60, replace=False))
+    s = ts.steps_per_period
+    for j in range(60):
+        k, i, X = int(d["k"][j]), int(d["rate"][j]), d["state"][j].astype(np.float64)
+        first = k // s
+        assert first <= i < ts.n_rates
+        L = ts.L0 * np.exp(X)
+        C = -o.drift(k, L)[i] - o.kappa[k, i]
+        ell = ts.delta * L / (1 + ts.delta * L)
+        lam = ts.vol[k]
+        C1 = sum(ell[l] * (_kappa(lam[i] + lam[l], ts) - _kappa(lam[i], ts) - _kappa(lam[l], ts))
+                 for l in range(i + 1, ts.n_rates))
+        assert abs(d["label"][j] - (C - C1)) <= 1e-6 * abs(C) + 1e-12, (j, d["label"][j], C - C1)
+        f = d["feat"][j]
+        T = np.concatenate([[0.0], ts.tenor])
+        tk = T[first] + (k - first * s) * (T[first + 1] - T[first]) / s
+        assert f[0] == M.bf16(tk / ts.tenor[-1])
+        assert np.array_equal(f[1:1 + i + 1], np.zeros(i + 1))
+        assert np.array_equal(f[1 + i + 1:41], M.bf16(X[i + 1:]))
+        assert f[41 + i] == 1.0 and np.sum(f[41:]) == 1.0
+    # the trust box holds every recorded state of a live rate
+    assert np.all(info["lo"] <= 0.0) and np.all(info["hi"][:-1] >= 0.0)
+
+
+def test_training_reduces_loss(gpu_lib):
+    ts = workloads.learned_drift()
+    with gpu_lib.Plan(ts, precision=0, max_paths=1024) as plan, gpu_lib.Mlp(seed=1) as net:
+        net.generate(plan, 2048, 16, seed=2)
+        loss = net.train(400, batch=4096, lr=2e-3, seed=3)
+    assert np.all(np.isfinite(loss))
+    assert loss[-40:].mean() < 0.1 * loss[:10].mean(), (loss[:10].mean(), loss[-40:].mean())
+
+
+@pytest.fixture(scope="module")
+def trained(gpu_lib):
+    """The N=40 quarterly workload's surrogate, trained on ~2^22 quadrature pairs."""
+    ts = workloads.learned_drift()
+    plan = gpu_lib.Plan(ts, precision=0, max_paths=1 << 16)
+    net = gpu_lib.Mlp(seed=1)
+    n_pairs = net.generate(plan, 12800, 16, seed=1)
+    loss = net.train(3000, batch=16384, lr=2e-3, seed=1)
+    yield ts, plan, net, n_pairs, loss
+    net.close()
+    plan.close()
+
+
+def test_surrogate_gain_over_first_order(gpu_lib, trained):
+    """Prices on common random numbers: the surrogate against the FULL quadrature
+    drift, next to the first-order expansion alone, Picard and the frozen drift."""
+    ts, plan, net, n_pairs, loss = trained
+    n = 1 << 16
+    assert n_pairs >= 4_000_000
+    res = {}
+    plan.execute(FULL, n, seed=1)
+    res["full"] = plan.results()["price"]
+    plan.execute(PICARD, n, seed=1)
+    res["picard"] = plan.results()["price"]
+    plan.execute(2, n, seed=1)
+    res["frozen"] = plan.results()["price"]
+    plan.execute_mlp(None, False, n, seed=1)
+    res["first_order"] = plan.results()["price"]
+    plan.execute_mlp(net, True, n, seed=1, judge_stride=8)
+    res["mlp"] = plan.results()["price"]
+    stats = plan.mlp_stats()
+    err = {k: np.max(np.abs(v / res["full"] - 1.0)) for k, v in res.items()}
+    print("max relative price error vs FULL:", {k: f"{v:.2e}" for k, v in err.items()})
+    print("judge:", stats, "final loss", float(loss[-50:].mean()))
+    assert err["mlp"] <= 1e-4
+    assert err["mlp"] < err["first_order"]
+    assert err["frozen"] > err["mlp"]
+    assert stats["fallbacks"] <= 1e-3 * stats["rate_steps"]
+    assert stats["judged"] > 0
+    assert stats["judge_abs_err"] / stats["judge_abs_quad"] < 1e-4
