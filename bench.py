@@ -118,6 +118,73 @@ def bench_adjoint(lll, stream, n: int = 1 << 20) -> dict:
             "fp32_tflops": fl / t / 1e12, "frac_fp32_peak": fl / t / PEAK_FP32}
 
 
+PEAK_BF16 = 2.5e15     # MI355X dense BF16 matrix cores, FLOP/s
+
+
+def mlp_flops_per_rate_step(n_later: int) -> dict:
+    """Algorithmic flops of the surrogate coupling of one rate with n_later later
+    rates (FMA = 2): matrix cores 2 x 64x64 layers x 64-wide FMA; vector ALU the
+    first-order expansion (2 per later rate), the first layer's suffix update
+    and pre-activation (6 per unit), three GELU layers (12 per unit), the
+    output dot (128) and the hidden biases (128)."""
+    return {"mfma": 2 * 2 * 64 * 64, "valu": 2 * n_later + 6 * 64 + 3 * 12 * 64 + 128 + 128}
+
+
+def bench_mlp(lll, stream, n: int = 1 << 20, train_steps: int = 3000) -> dict:
+    """Learned drift (N=40 quarterly, 2^20 paths): datagen (~2^22 quadrature
+    pairs), training on the device, then FULL, Picard, the first-order
+    expansion alone and the surrogate on common random numbers, each judged
+    against FULL (max relative caplet error over all caplets and strikes)."""
+    ts = workloads.learned_drift()
+    out = {"workload": ts.name, "n_paths": n}
+    with lll.Plan(ts, precision=lll.FP32, max_paths=n) as plan, lll.Mlp(seed=1) as net:
+        plan.set_timing(True)
+        t0 = time.perf_counter()
+        pairs = net.generate(plan, 12800, 16, seed=1, stream=stream)
+        t1 = time.perf_counter()
+        loss = net.train(train_steps, batch=16384, lr=2e-3, seed=1, stream=stream)
+        t2 = time.perf_counter()
+        out["train"] = {"pairs": pairs, "datagen_s": t1 - t0, "train_s": t2 - t1,
+                        "steps": train_steps, "batch": 16384,
+                        "loss_first": float(loss[:10].mean()), "loss_last": float(loss[-50:].mean())}
+        legs = [("full", lambda: plan.execute(lll.FULL, n, seed=1, stream=stream)),
+                ("picard", lambda: plan.execute(lll.PICARD, n, seed=1, stream=stream)),
+                ("frozen", lambda: plan.execute(lll.FROZEN, n, seed=1, stream=stream)),
+                ("first_order", lambda: plan.execute_mlp(None, False, n, seed=1, stream=stream)),
+                ("mlp", lambda: plan.execute_mlp(net, True, n, seed=1, stream=stream))]
+        prices = {}
+        for name, run in legs:
+            run()                       # warmup
+            run()
+            ms = plan.timing()["paths"]
+            prices[name] = plan.results(stream)["price"]
+            out[name] = {"kernel_ms": ms, "path_steps_per_s": n * ts.n_steps / (ms / 1e3)}
+        live = prices["full"] > 0.0    # out-of-the-money caplets fixed at t = 0 price 0
+        for name in prices:
+            rel = np.abs(prices[name][live] / prices["full"][live] - 1)
+            out[name]["max_rel_err_vs_full"] = float(np.max(rel))
+        plan.execute_mlp(net, True, n, seed=1, judge_stride=8, stream=stream)
+        st = plan.mlp_stats(stream)
+        out["mlp"]["judge"] = {"stride": 8, "rate_steps": st["rate_steps"],
+                               "fallback_frac": st["fallbacks"] / st["rate_steps"],
+                               "mean_abs_err_over_mean_abs_quad": st["judge_abs_err"] / st["judge_abs_quad"],
+                               "max_rel": st["judge_max_rel"]}
+    s, N = ts.steps_per_period, ts.n_rates
+    mf = va = 0
+    for m in range(N):
+        for i in range(m, N):
+            f = mlp_flops_per_rate_step(N - 1 - i)
+            mf += s * f["mfma"]
+            va += s * f["valu"]
+    t = out["mlp"]["kernel_ms"] / 1e3
+    out["mlp"].update({"mfma_tflops": mf * n / t / 1e12, "frac_bf16_peak": mf * n / t / PEAK_BF16,
+                       "valu_tflops": va * n / t / 1e12, "frac_fp32_peak": va * n / t / PEAK_FP32})
+    for name in ("full", "picard"):
+        fl = flops_per_path(ts, name) * n
+        out[name]["frac_fp32_peak"] = fl / (out[name]["kernel_ms"] / 1e3) / PEAK_FP32
+    return out
+
+
 def bench_batched(lll, stream, schemes, n_each: int = 1 << 18, reps: int = 2) -> dict:
     """64 independent structures in one persistent launch: kernel time (HIP events
     recorded by the library), path-steps/s and FP32 fraction of peak."""
@@ -152,6 +219,8 @@ def main(argv=None) -> int:
                     help="also time the 64-structure persistent launch (2^18 paths each)")
     ap.add_argument("--adjoint", type=int, default=1,
                     help="also time the pathwise Greeks pass (N=40, 2^20 paths)")
+    ap.add_argument("--mlp", type=int, default=1,
+                    help="also train the drift surrogate and time it (N=40, 2^20 paths)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (a kernel of "
                          "known traffic for calibrating HBM counters)")
@@ -250,6 +319,8 @@ def main(argv=None) -> int:
         out["batched"] = bench_batched(lll, stream, schemes)
     if args.adjoint:
         out["adjoint"] = bench_adjoint(lll, stream)
+    if args.mlp:
+        out["mlp"] = bench_mlp(lll, stream)
     if args.cpu_sample > 0:
         out["cpu_baseline"] = cpu_baseline(ts, args.cpu_sample, schemes)
     plan.close()

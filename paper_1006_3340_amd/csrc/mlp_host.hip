@@ -406,15 +406,22 @@ int lll_plan_execute_mlp(lll_plan *plan, const lll_mlp *m, int use_net, int64_t 
     const float *zw = static_cast<const float *>(b.zero_params);
     const float *wts = m ? m->wts : zw;
     const __bf16 *wbf = m ? m->wbf : reinterpret_cast<const __bf16 *>(zw + kParams);
-    e = lll::launch_precompute(*plan, st);
+    // timing stages as in lll_plan_execute: tables, path kernel, reduction
+    const bool t = plan->timing;
+    e = t ? hipEventRecord(plan->ev[0], st) : hipSuccess;
+    if (e == hipSuccess) e = lll::launch_precompute(*plan, st);
     if (e == hipSuccess) e = launch_mlp_tables(*plan, wts, b.K2, b.tnorm, b.W1T, st);
     const float *box = use_net ? m->info : b.open_box;
     const float sigma = use_net ? m->info_host[2 * kRates] : 0.0f;
+    if (e == hipSuccess && t) e = hipEventRecord(plan->ev[1], st);
     if (e == hipSuccess)
         e = launch_mlp_paths(*plan, wts, wbf, b.K2, b.tnorm, b.W1T, box, sigma, use_net,
                              judge_stride, n_paths, seed, path_fix_dev, b.stats, st);
+    if (e == hipSuccess && t) e = hipEventRecord(plan->ev[2], st);
     if (e == hipSuccess) e = lll::launch_reduce(*plan, n_paths, st);
+    if (e == hipSuccess && t) e = hipEventRecord(plan->ev[3], st);
     if (e != hipSuccess) return hip_fail(e, "surrogate path launch");
+    plan->timed = t;
     plan->last_n_paths = n_paths;
     plan->executed = true;
     plan->mlp_done = true;
