@@ -209,6 +209,14 @@ int lll_mlp_generate(lll_mlp *mlp, lll_plan *plan, int64_t n_paths, int records,
 /* info_host[81]: box minimum per rate [40], box maximum per rate [40], sigma. */
 int lll_mlp_info(lll_mlp *mlp, float *info_host, int64_t *n_pairs);
 
+/* Replace the trust box (box_host[80]: minimum per rate [40], maximum per rate
+ * [40], in units of X_l = log L_l - log L_l(0)) that lll_mlp_generate set.  A
+ * rate whose later rates leave the box takes the quadrature coupling; an
+ * empty box (minimum above maximum) sends every coupling to the quadrature.
+ * Needs generated data (LLL_EINVAL otherwise); NaN entries are rejected.
+ * Synchronous. */
+int lll_mlp_set_box(lll_mlp *mlp, const float *box_host);
+
 /* For pairs[n]: the recorded state [n][40] (FP32, by rate), its step, the
  * pair's rate, its label and its features [n][96] (BF16 values as FP32).
  * Any output may be NULL. */

@@ -50,11 +50,11 @@ C0 = math.sqrt(2.0 / math.pi)
 
 
 def gelu(x):
-    return 0.5 * x * (1.0 + np.tanh(C0 * (x + 0.044715 * x ** 3)))
+    return 0.5 * x * (1.0 + np.tanh(C0 * (x + 0.044715 * x * x * x)))
 
 
 def gelu_grad(x):
-    u = C0 * (x + 0.044715 * x ** 3)
+    u = C0 * (x + 0.044715 * x * x * x)
     t = np.tanh(u)
     du = C0 * (1.0 + 3.0 * 0.044715 * x * x)
     return 0.5 * (1.0 + t) + 0.5 * x * (1.0 - t * t) * du
@@ -95,3 +95,114 @@ def loss_and_grad(p, X, t, bf=False):
     g["W1"] = r(dz1).T @ c["X"]
     g["b1"] = dz1.sum(axis=0)
     return loss, pack(g)
+
+
+# ---------------------------------------------------------------------------
+# Euler paths with the surrogate drift
+# ---------------------------------------------------------------------------
+
+def nig_kappa(u, alpha, beta, delta):
+    """NIG cumulant kappa(u) = log E[e^{u H_1}] with the martingale location
+    mu = -delta beta / gamma (Section 2's log moment generating function)."""
+    gamma = math.sqrt(alpha * alpha - beta * beta)
+    mu = -delta * beta / gamma
+    u = np.asarray(u, dtype=np.float64)
+    return mu * u + delta * (gamma - np.sqrt(alpha * alpha - (beta + u) ** 2))
+
+
+def first_order_coupling(ell, lam, ts):
+    """First-order expansion of the coupling (Section 3.2, eq. (drifta)):
+    C'_i = sum_{l>i} ell_l [kappa(lam_i + lam_l) - kappa(lam_i) - kappa(lam_l)].
+    ell: [..., N]; lam: [N]; returns [..., N]."""
+    k1 = nig_kappa(lam, ts.alpha, ts.beta, ts.delta_nig)
+    k2 = nig_kappa(lam[:, None] + lam[None, :], ts.alpha, ts.beta, ts.delta_nig)
+    K2 = np.triu(k2 - k1[:, None] - k1[None, :], 1)     # [i, l], l > i only
+    return ell @ K2.T
+
+
+def features(tn, X, i):
+    """Inputs of the network for rate i at normalised time tn and states X[n, 40]
+    (log L_l - log L_l(0)); rates l <= i are zeroed; one-hot of i."""
+    n = X.shape[0]
+    f = np.zeros((n, N_IN))
+    f[:, 0] = tn
+    f[:, 2 + i:41] = X[:, i + 1:40]
+    f[:, 41 + i] = 1.0
+    return f
+
+
+def surrogate_paths(o, params, lo, hi, sigma, paths, use_net=True):
+    """FP64 Euler paths (eq. (LIBOR-drift-PT)) of the given path indices with
+    the coupling C_i replaced by C'_i + sigma * net(features_i), or by C'_i alone
+    when use_net is False; the last rate has no coupling.  A rate whose later
+    rates leave the box [lo, hi] (compared in FP32, as the device compares)
+    takes the quadrature coupling of the oracle instead.  The increments are the
+    oracle's (same Philox streams).  Returns payoff sums in the layout of
+    Oracle.price_sums and the per-path fixings (L_c, D_c), each [n, N].
+    Needs a structure of 40 rates."""
+    ts = o.ts
+    N, s, K = o.N, o.s, o.K
+    assert N == 40
+    paths = np.asarray(paths, dtype=np.int64)
+    n = len(paths)
+    contiguous = n > 0 and np.array_equal(paths, paths[0] + np.arange(n))
+    L0 = np.asarray(ts.L0, dtype=np.float64)
+    delta = np.asarray(ts.delta, dtype=np.float64)
+    strikes = np.asarray(ts.strikes, dtype=np.float64)
+    lo32 = np.asarray(lo, dtype=np.float32)
+    hi32 = np.asarray(hi, dtype=np.float32)
+    T = np.concatenate([[0.0], np.asarray(ts.tenor, dtype=np.float64)])
+    X = np.zeros((n, N))
+    Lfix = np.zeros((n, N))
+    Dfix = np.zeros((n, N))
+    S = strikes.shape[1]
+    sp = np.zeros((N, S)); sp2 = np.zeros((N, S)); itm = np.zeros((N, S))
+    mart = np.zeros(N); mart2 = np.zeros(N)
+    fallbacks = 0
+    for k in range(K):
+        m = k // s
+        if contiguous:
+            _, dH = o.increments(k, int(paths[0]), n)
+        else:
+            dH = np.array([o.increments(k, int(p), 1)[1][0] for p in paths])
+        lam = np.asarray(ts.vol[k], dtype=np.float64)
+        L = L0 * np.exp(X)
+        ell = delta * L / (1.0 + delta * L)
+        ell[:, :m] = 0.0
+        C = first_order_coupling(ell, lam, ts)
+        if use_net:
+            tk = T[m] + (k - m * s) * (T[m + 1] - T[m]) / s
+            tn = float(np.float32(tk / T[N]))
+            rates = range(m, N - 1)
+            if len(rates):
+                y, _ = forward(params, np.concatenate([features(tn, X, i) for i in rates]), bf=True)
+                C[:, m:N - 1] += sigma * y.reshape(len(rates), n).T
+            X32 = X.astype(np.float32)
+            out = ((X32 < lo32) | (X32 > hi32)).astype(np.int64)
+            out[:, :m] = 0
+            later = np.cumsum(out[:, ::-1], axis=1)[:, ::-1]     # later[p, i] = #out l >= i
+            fb = np.zeros((n, N), dtype=bool)
+            fb[:, :N - 1] = later[:, 1:] > 0
+            fb[:, :m] = False
+            for p in np.nonzero(fb.any(axis=1))[0]:
+                b = o.drift(k, L[p])
+                quad = -b - o.kappa[k]
+                C[p, fb[p]] = quad[fb[p]]
+            fallbacks += int(fb.sum())
+        C[:, N - 1] = 0.0
+        X[:, m:] += (-o.kappa[k, m:] - C[:, m:]) * o.dt[k] + lam[m:] * dH[:, None]
+        if (k + 1) % s == 0:
+            c = m
+            Lc = L0[c] * np.exp(X[:, c])
+            D = np.prod(1.0 + delta[c + 1:] * L0[c + 1:] * np.exp(X[:, c + 1:]), axis=1)
+            Lfix[:, c], Dfix[:, c] = Lc, D
+            pay = D[:, None] * np.maximum(Lc[:, None] - strikes[c][None, :], 0.0)
+            sp[c] = pay.sum(axis=0)
+            sp2[c] = (pay * pay).sum(axis=0)
+            itm[c] = (Lc[:, None] > strikes[c][None, :]).sum(axis=0)
+            mt = D * (1.0 + delta[c] * Lc)
+            mart[c] = mt.sum()
+            mart2[c] = (mt * mt).sum()
+    sums = {"sum_p": sp, "sum_p2": sp2, "n_itm": itm, "sum_mart": mart, "sum_mart2": mart2,
+            "n_paths": n, "fallbacks": fallbacks}
+    return sums, Lfix, Dfix

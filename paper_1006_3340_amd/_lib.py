@@ -30,7 +30,7 @@ EXPORTS = ["lll_version", "lll_last_error", "lll_plan_create", "lll_plan_execute
            "lll_batch_execute", "lll_batch_results", "lll_batch_set_timing", "lll_batch_timing",
            "lll_batch_destroy", "lll_plan_greeks", "lll_plan_greeks_results", "lll_caplet_greeks",
            "lll_mlp_create", "lll_mlp_destroy", "lll_mlp_params", "lll_mlp_generate",
-           "lll_mlp_info", "lll_mlp_pairs", "lll_mlp_train", "lll_mlp_eval",
+           "lll_mlp_info", "lll_mlp_set_box", "lll_mlp_pairs", "lll_mlp_train", "lll_mlp_eval",
            "lll_plan_execute_mlp", "lll_plan_mlp_stats"]
 MLP_PARAMS, MLP_INPUTS = 14593, 96
 
@@ -98,6 +98,7 @@ def load():
     lib.lll_mlp_params.argtypes = [vp, fp, fp]
     lib.lll_mlp_generate.argtypes = [vp, vp, i64, i32, u64, i64p, vp]
     lib.lll_mlp_info.argtypes = [vp, fp, i64p]
+    lib.lll_mlp_set_box.argtypes = [vp, fp]
     lib.lll_mlp_pairs.argtypes = [vp, i64p, i64, fp, i32p, i32p, fp, fp]
     lib.lll_mlp_train.argtypes = [vp, i32, i32, ctypes.c_float, u64, fp, vp]
     lib.lll_mlp_eval.argtypes = [vp, fp, fp, i64, fp, fp, fp, vp]
@@ -399,6 +400,12 @@ class Mlp:
         _check(self.lib.lll_mlp_info(self.h, _fp(out), ctypes.byref(n)))
         return {"lo": out[:40].copy(), "hi": out[40:80].copy(), "sigma": float(out[80]),
                 "n_pairs": n.value}
+
+    def set_box(self, lo: np.ndarray, hi: np.ndarray):
+        box = np.ascontiguousarray(np.concatenate([np.asarray(lo, dtype=np.float32).ravel(),
+                                                   np.asarray(hi, dtype=np.float32).ravel()]))
+        assert box.shape == (80,)
+        _check(self.lib.lll_mlp_set_box(self.h, _fp(box)))
 
     def pairs(self, idx) -> dict:
         idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int64))

@@ -253,6 +253,17 @@ int lll_mlp_info(lll_mlp *m, float *info_host, int64_t *n_pairs) {
     return LLL_OK;
 }
 
+int lll_mlp_set_box(lll_mlp *m, const float *box_host) {
+    if (!m || !box_host) return fail(LLL_EINVAL, "NULL argument");
+    if (!m->have_data) return fail(LLL_EINVAL, "no training data generated");
+    for (int i = 0; i < 2 * kRates; ++i)
+        if (std::isnan(box_host[i])) return fail(LLL_EINVAL, "box entry %d is NaN", i);
+    hipError_t e = hipMemcpy(m->info, box_host, sizeof(float) * 2 * kRates, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "setting the trust box");
+    std::memcpy(m->info_host, box_host, sizeof(float) * 2 * kRates);
+    return LLL_OK;
+}
+
 int lll_mlp_pairs(lll_mlp *m, const int64_t *pairs, int64_t n, float *state_host, int *k_host,
                   int *rate_host, float *label_host, float *feat_host) {
     if (!m || !pairs) return fail(LLL_EINVAL, "NULL argument");

@@ -214,7 +214,8 @@ __global__ void __launch_bounds__(kBlock) mlp_path_kernel(PathArgs<float> a, Mlp
 #pragma unroll
             for (int jj = 0; jj < kSlots; ++jj) c1 = fmaf(ell[jj], K2row[jj], c1);
             float y = 0.0f;
-            if (g.use_net) {
+            // the last live slot has no later rate: its coupling is exactly 0
+            if (g.use_net && j < kSlots - 1) {
                 // layer 1 from the suffix sum of the later rates
                 const cptr<float> w0 = g.W1T;                     // t_k column
                 const cptr<float> wi = g.W1T + (1 + kRates + r) * kHid;  // one-hot column
@@ -233,6 +234,8 @@ __global__ void __launch_bounds__(kBlock) mlp_path_kernel(PathArgs<float> a, Mlp
                 y = g.wf[kOffB4];
 #pragma unroll
                 for (int h = 0; h < kHid; ++h) y = fmaf(g.wf[kOffW4 + h], static_cast<float>(row[h]), y);
+            }
+            if (g.use_net) {
                 // this rate's state joins the suffix sum of the next (lower) rate
                 float xj = 0.0f;
 #pragma unroll

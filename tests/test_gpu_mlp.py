@@ -112,9 +112,10 @@ def test_training_reduces_loss(gpu_lib):
 
 @pytest.fixture(scope="module")
 def trained(gpu_lib):
-    """The N=40 quarterly workload's surrogate, trained on ~2^22 quadrature pairs."""
+    """The N=40 quarterly workload's surrogate, trained on ~2^22 quadrature pairs
+    (the benchmark's datagen and training configuration)."""
     ts = workloads.learned_drift()
-    plan = gpu_lib.Plan(ts, precision=0, max_paths=1 << 16)
+    plan = gpu_lib.Plan(ts, precision=0, max_paths=1 << 20)
     net = gpu_lib.Mlp(seed=1)
     n_pairs = net.generate(plan, 12800, 16, seed=1)
     loss = net.train(3000, batch=16384, lr=2e-3, seed=1)
@@ -123,11 +124,86 @@ def trained(gpu_lib):
     plan.close()
 
 
+def _surrogate_oracle(oracle_mod, ts, net, paths, use_net=True):
+    o = oracle_mod.Oracle(ts)
+    info = net.info()
+    return M.surrogate_paths(o, net.params().astype(np.float64), info["lo"], info["hi"],
+                             info["sigma"], paths, use_net=use_net)
+
+
+@pytest.mark.parametrize("use_net", [True, False])
+def test_surrogate_paths_match_oracle(gpu_lib, oracle_mod, trained, use_net):
+    """Per-path fixings of the surrogate scheme (and of the first-order scheme)
+    against the FP64 oracle of the same scheme with the same weights, box and
+    streams: the FP32 path tolerance of the FULL scheme (2e-5 relative)."""
+    import torch
+    ts, plan, net, _, _ = trained
+    n = 128
+    fix = torch.empty((n, 2 * ts.n_rates), dtype=torch.float64, device="cuda")
+    plan.execute_mlp(net if use_net else None, use_net, n, seed=1, judge_stride=1, path_fix=fix)
+    torch.cuda.synchronize()
+    f = fix.cpu().numpy()
+    sums, Lo, Do = _surrogate_oracle(oracle_mod, ts, net, np.arange(n), use_net)
+    assert np.all(np.abs(f[:, 0::2] / Lo - 1.0) < 2e-5)
+    assert np.all(np.abs(f[:, 1::2] / Do - 1.0) < 2e-5)
+    ref = oracle_mod.finish(sums, ts.delta, ts.L0, ts.B0_T1 / np.prod(1.0 + ts.delta * ts.L0))
+    got = plan.results()
+    live = ref["price"] > 0
+    assert np.all(np.abs(got["price"][live] / ref["price"][live] - 1.0) < 1e-4)
+    st = plan.mlp_stats()
+    assert st["rate_steps"] == n * sum(ts.n_rates - k // ts.steps_per_period
+                                       for k in range(ts.n_steps))
+    if not use_net:
+        assert st["fallbacks"] == 0
+
+
+def test_surrogate_full_size_sampled_paths(gpu_lib, oracle_mod, trained):
+    """The benchmark launch (2^20 paths): sampled per-path fixings against the
+    oracle of the surrogate scheme."""
+    import torch
+    ts, plan, net, _, _ = trained
+    n = 1 << 20
+    fix = torch.empty((n, 2 * ts.n_rates), dtype=torch.float64, device="cuda")
+    plan.execute_mlp(net, True, n, seed=1, path_fix=fix)
+    torch.cuda.synchronize()
+    f = fix.cpu().numpy()
+    sample = np.array([0, 4095, 77777, 524288, n - 1])
+    _, Lo, Do = _surrogate_oracle(oracle_mod, ts, net, sample)
+    assert np.all(np.abs(f[sample, 0::2] / Lo - 1.0) < 2e-5)
+    assert np.all(np.abs(f[sample, 1::2] / Do - 1.0) < 2e-5)
+
+
+def test_empty_trust_box_is_full_euler(gpu_lib, trained):
+    """An empty trust box sends every coupling to the quadrature: the surrogate
+    pass must then reproduce the FULL pass bit for bit."""
+    ts, plan, net, _, _ = trained
+    n = 1 << 14
+    info = net.info()
+    plan.execute(FULL, n, seed=3)
+    full = plan.results()
+    try:
+        net.set_box(np.ones(40), -np.ones(40))
+        plan.execute_mlp(net, True, n, seed=3)
+        got = plan.results()
+        st = plan.mlp_stats()
+    finally:
+        net.set_box(info["lo"], info["hi"])
+    assert np.array_equal(got["price"], full["price"])
+    assert np.array_equal(got["mart_resid"], full["mart_resid"])
+    # every coupled rate-step fell back; the last rate has no coupling
+    s = ts.steps_per_period
+    coupled = n * sum(ts.n_rates - 1 - k // s for k in range(ts.n_steps) if k // s < ts.n_rates - 1)
+    assert st["fallbacks"] == coupled
+    with pytest.raises(gpu_lib.LLLError):
+        net.set_box(np.full(40, np.nan), np.ones(40))
+
+
 def test_surrogate_gain_over_first_order(gpu_lib, trained):
-    """Prices on common random numbers: the surrogate against the FULL quadrature
-    drift, next to the first-order expansion alone, Picard and the frozen drift."""
+    """Prices on common random numbers at the benchmark size (2^20 paths): the
+    surrogate against the FULL quadrature drift, next to the first-order
+    expansion alone, Picard and the frozen drift."""
     ts, plan, net, n_pairs, loss = trained
-    n = 1 << 16
+    n = 1 << 20
     assert n_pairs >= 4_000_000
     res = {}
     plan.execute(FULL, n, seed=1)

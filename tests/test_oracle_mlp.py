@@ -54,3 +54,70 @@ def test_bf16_rounding():
     assert r[3] == 1.0 + 2**-7                # above half an ulp
     assert abs(r[4] + 3.140625) < 1e-12
     assert r[5] == 0.0
+
+
+def test_first_order_expansion_error_is_second_order(oracle_mod):
+    """The first-order coupling C' of eq. (drifta) approaches the product-form
+    coupling of eq. (LIBOR-drift-PT) with an error of order ell^2: its relative
+    error halves when all forwards halve (Section 3.2)."""
+    import workloads
+    rel = []
+    for f in (4e-3, 2e-3, 1e-3):
+        ts = workloads.learned_drift()
+        ts.L0 = ts.L0 * f
+        o = oracle_mod.Oracle(ts)
+        for k in (0, 137):
+            m = k // ts.steps_per_period
+            L = np.asarray(ts.L0, dtype=np.float64)
+            C = -o.drift(k, L) - o.kappa[k]
+            ell = ts.delta * L / (1 + ts.delta * L)
+            ell[:m] = 0.0
+            C1 = M.first_order_coupling(ell[None, :], np.asarray(ts.vol[k]), ts)[0]
+            i = m  # first live rate: the longest coupling sum
+            assert np.sign(C1[i]) == np.sign(C[i])
+            rel.append(abs(C1[i] / C[i] - 1.0))
+            assert C[-1] == 0.0 and C1[-1] == 0.0
+    r = np.array(rel).reshape(3, 2)
+    ratios = r[:-1] / r[1:]
+    assert np.all(np.abs(ratios - 2.0) < 0.05), ratios
+    assert np.all(r[0] < 1e-3)
+
+
+def test_surrogate_paths_with_empty_box_are_full_euler(oracle_mod):
+    """With an empty trust box every coupling falls back to the quadrature, so
+    the surrogate scheme must reproduce the FULL Euler paths of the C oracle
+    (same streams, same payoff sums) up to FP64 rounding order."""
+    import workloads
+    ts = workloads.learned_drift()
+    o = oracle_mod.Oracle(ts)
+    rng = np.random.default_rng(5)
+    p = _random_params(rng)
+    lo, hi = np.ones(40), -np.ones(40)
+    sums, Lf, Df = M.surrogate_paths(o, p, lo, hi, 0.01, np.arange(8))
+    ref = o.price_sums(0, 8)
+    Lo, Do = o.paths(0, np.arange(8))
+    assert np.allclose(Lf, Lo, rtol=1e-12, atol=0)
+    assert np.allclose(Df, Do, rtol=1e-12, atol=0)
+    assert np.allclose(sums["sum_p"], ref["sum_p"], rtol=1e-10, atol=1e-300)
+    assert np.array_equal(sums["n_itm"], ref["n_itm"])
+    assert np.allclose(sums["sum_mart"], ref["sum_mart"], rtol=1e-12)
+    assert sums["fallbacks"] == 8 * sum(39 - k // 10 for k in range(400) if k // 10 < 39)
+    # sparse path indices take the same streams as a contiguous range
+    s2, L2, _ = M.surrogate_paths(o, p, lo, hi, 0.01, np.array([3, 6]))
+    assert np.allclose(L2, Lo[[3, 6]], rtol=1e-12, atol=0)
+
+
+def test_surrogate_paths_first_order_close_to_full(oracle_mod):
+    """With the first-order coupling alone the fixings stay within the O(ell^2)
+    drift error of the FULL paths; with a network that outputs exactly zero
+    (all weights 0) the surrogate scheme is the first-order scheme."""
+    import workloads
+    ts = workloads.learned_drift()
+    o = oracle_mod.Oracle(ts)
+    big = np.full(40, 1e30)
+    s1, L1, _ = M.surrogate_paths(o, np.zeros(M.N_PARAMS), -big, big, 1.0, np.arange(4))
+    s0, L0f, _ = M.surrogate_paths(o, None, -big, big, 1.0, np.arange(4), use_net=False)
+    assert np.array_equal(L1, L0f)
+    Lo, _ = o.paths(0, np.arange(4))
+    d = np.abs(L0f / Lo - 1.0)
+    assert 0 < d.max() < 1e-3
