@@ -259,7 +259,10 @@ typedef struct lll_batch lll_batch;
 
 /* Validate all n_ts structures (host array ts[n_ts]) and allocate their
  * device tables and buffers for up to max_paths_each paths per structure.
- * Each structure's struct_id is its fourth Philox counter word.  Synchronous. */
+ * Each structure's struct_id is its fourth Philox counter word.  Limits:
+ * 1 <= n_ts <= 4096, 1 <= max_paths_each <= 2^30 and n_ts x ceil(max_paths_each
+ * / 256) <= 2^30 (one work item per block of 256 paths), else LLL_EINVAL.
+ * Synchronous. */
 int lll_batch_create(const lll_term_structure *ts, int n_ts, int64_t max_paths_each,
                      lll_batch **batch_out);
 

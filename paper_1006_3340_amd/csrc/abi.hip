@@ -465,6 +465,13 @@ int lll_batch_create(const lll_term_structure *ts, int n_ts, int64_t max_paths_e
     if (!ts || n_ts < 1 || n_ts > 4096) return fail(LLL_EINVAL, "n_ts=%d outside 1..4096", n_ts);
     if (max_paths_each < 1 || max_paths_each > ((int64_t)1 << 30))
         return fail(LLL_EINVAL, "max_paths_each=%lld outside 1..2^30", (long long)max_paths_each);
+    // one work item per block of 256 paths of every structure; the device
+    // counter is a 32-bit int that every resident block bumps once past the
+    // end, so the item count stays well below 2^31
+    const int64_t items = (max_paths_each + 255) / 256 * n_ts;
+    if (items > ((int64_t)1 << 30))
+        return fail(LLL_EINVAL, "n_ts x max_paths_each / 256 = %lld work items exceeds 2^30",
+                    (long long)items);
     for (int i = 0; i < n_ts; ++i) {
         int rc = validate(&ts[i]);
         if (rc != LLL_OK) {
@@ -484,8 +491,7 @@ int lll_batch_create(const lll_term_structure *ts, int n_ts, int64_t max_paths_e
         }
         b->plans.push_back(p);
     }
-    const int64_t blocks = (max_paths_each + 255) / 256;
-    b->max_items = static_cast<int>(blocks * n_ts);
+    b->max_items = static_cast<int>(items);
     hipError_t e = hipMalloc(&b->args, n_ts * lll::batch_args_bytes());
     if (e == hipSuccess) e = hipMalloc(&b->items, (size_t)b->max_items * lll::batch_item_bytes());
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&b->counter), 256);

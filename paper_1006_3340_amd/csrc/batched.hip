@@ -1,7 +1,7 @@
 // batched.hip -- many independent term structures in one persistent launch.
 //
 // Work items are (structure, block of 256 paths), sorted by decreasing cost
-// (N s per path) on the host.  A grid sized to the resident capacity of the
+// (N^2 s per path) on the host.  A grid sized to the resident capacity of the
 // GPU pulls items from an atomic counter until none are left, so long tenors
 // start first and the tail is filled by short ones.  Every structure uses the
 // 40-slot register bucket (its rates occupy the top N slots) and its own
@@ -49,6 +49,8 @@ template <int SCHEME>
 __global__ void __launch_bounds__(kBlock) batched_kernel(cptr<PathArgs<float>> args,
                                                          cptr<BatchItem> items, int n_items,
                                                          int *__restrict__ counter) {
+    // The block shares one item (its four wavefronts then stream the same
+    // step tables through the CU's scalar cache).
     __shared__ int s_item;
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
@@ -60,7 +62,7 @@ __global__ void __launch_bounds__(kBlock) batched_kernel(cptr<PathArgs<float>> a
         const PathArgs<float> a = load_uniform<PathArgs<float>>(args + it.s);
         const int64_t gid = it.first + threadIdx.x;
         const int64_t wave_first = gid - (threadIdx.x % kWave);
-        if (wave_first < a.n_paths) detail::simulate<float, kBatchSlots, SCHEME>(a, gid);
+        if (wave_first < a.n_paths) detail::simulate<float, kBatchSlots, SCHEME, false>(a, gid);
     }
 }
 

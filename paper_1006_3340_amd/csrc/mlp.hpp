@@ -38,10 +38,15 @@ constexpr int kParams = kOffB4 + 1;  // 14593
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-// tanh-form GELU: 0.5 x (1 + tanh(sqrt(2/pi) (x + 0.044715 x^3))) = x / (1 + e^{-2u}).
+// tanh-form GELU: 0.5 x (1 + tanh(u)), u = sqrt(2/pi) (x + 0.044715 x^3),
+// = x / (1 + e^{-2u}) = x / (1 + 2^{x (a + b x^2)}) with a = -2 sqrt(2/pi) / ln 2
+// and b = 0.044715 a folded into one polynomial for the hardware base-2
+// exponential (which saturates to +inf / 0, giving 0 / x in the tails).
 __device__ __forceinline__ float gelu(float x) {
-    const float u = 0.7978845608028654f * fmaf(0.044715f * x, x * x, x);
-    return x * __builtin_amdgcn_rcpf(1.0f + __expf(-2.0f * u));
+    constexpr float a = -2.302208198144325f;
+    constexpr float b = -0.1029432395800235f;
+    const float p = x * fmaf(b, x * x, a);
+    return x * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(p));
 }
 
 // d gelu / dx for the same form.

@@ -8,10 +8,15 @@
 // use_net = 0 the kernel runs the first-order drift expansion alone.
 //
 // The network's first layer is a suffix sum over the rates (the features of
-// rate i are the states of the rates l > i), so it costs 64 FMAs per rate; the
-// two hidden 64x64 layers run on the matrix cores for the wave's 64 paths at
-// once: Z^T = W . H^T with W from LDS (shared by the block) and H staged per
-// wave in LDS, v_mfma_f32_16x16x32_bf16, FP32 accumulation.
+// rate i are the states of the rates l > i), so it costs 64 FMAs per rate plus
+// one add of a per-(step, rate) bias table (b1 + the time and one-hot
+// columns); the two hidden 64x64 layers run on the matrix cores for the
+// wave's 64 paths at once: Z^T = W . H^T with W from LDS (shared by the
+// block) and H staged per wave in LDS, v_mfma_f32_16x16x32_bf16, FP32
+// accumulation.  The state X and the couplings C live in LDS columns (one per
+// thread), so a rate's state and coupling are addressed by the loop index
+// without register selects.  Nothing is shared between wavefronts inside the
+// step loop, so the waves synchronise only with themselves.
 //
 // Fallback: a path whose later-rate state leaves the range seen in training
 // (per rate) takes the 64-node quadrature coupling for that rate instead.
@@ -38,30 +43,45 @@ constexpr int kSlots = kRates;  // the surrogate runs in the 40-slot bucket
 constexpr int kNStat = 8;
 
 struct MlpArgs {
-    cptr<float> W1T;    // [96][64] first layer, transposed
+    cptr<float> W1T;    // [96][64] first layer, transposed (BF16-rounded values)
     cptr<float> wf;     // FP32 parameter vector (biases, w4, b4)
     const __bf16 *W2;   // [64][64]
     const __bf16 *W3;   // [64][64]
     cptr<float> K2;     // [K][40][40]
     cptr<float> lo;     // [40] trust box per slot
     cptr<float> hi;
-    cptr<float> tnorm;  // [K] t_k / T_N
+    cptr<float> B1;     // [K][40][64] first-layer bias of (step, rate)
     double *stats;      // [waves][kNStat]
     float sigma;
     int use_net;
     int judge_stride;
 };
 
+// LDS of one wavefront's LDS-resident per-lane state: column `lane` of
+// [slot][kWave] arrays.
+struct LaneLds {
+    float *x;  // X_j at x[j * kWave]
+    float *c;  // C_j at c[j * kWave]
+};
+
+// Orders this wavefront's LDS accesses across lanes (all LDS data used inside
+// the step loop is private to the wavefront).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int J0>
 __device__ __forceinline__ void ell_and_box(const PathArgs<float> &a, const MlpArgs &g,
-                                            const float (&X)[kSlots], float (&ell)[kSlots],
-                                            uint64_t &oob) {
+                                            const LaneLds &s, float (&ell)[kSlots], uint64_t &oob) {
     oob = 0;
 #pragma unroll
     for (int j = 0; j < kSlots; ++j) {
         if (j >= J0) {
-            ell[j] = detail::ell_of(X[j], a.cinv[j]);
-            const bool out = (X[j] < g.lo[j]) || (X[j] > g.hi[j]);
+            const float x = s.x[j * kWave];
+            ell[j] = detail::ell_of(x, a.cinv[j]);
+            const bool out = (x < g.lo[j]) || (x > g.hi[j]);
             oob |= static_cast<uint64_t>(out) << j;
         } else {
             ell[j] = 0.0f;
@@ -72,17 +92,19 @@ __device__ __forceinline__ void ell_and_box(const PathArgs<float> &a, const MlpA
 template <int... Js>
 __device__ __forceinline__ void dispatch_ell(std::integer_sequence<int, Js...>, int j0,
                                              const PathArgs<float> &a, const MlpArgs &g,
-                                             const float (&X)[kSlots], float (&ell)[kSlots],
-                                             uint64_t &oob) {
-    (void)((j0 == Js ? (ell_and_box<Js>(a, g, X, ell, oob), 0) : 0) + ...);
+                                             const LaneLds &s, float (&ell)[kSlots], uint64_t &oob) {
+    (void)((j0 == Js ? (ell_and_box<Js>(a, g, s, ell, oob), 0) : 0) + ...);
 }
 
 // Quadrature coupling for the judge and the fallback, plus the state update.
 template <int J0>
 __device__ __forceinline__ void finish_step(const PathArgs<float> &a, const MlpArgs &g, int k,
                                             float dH, bool need_quad, bool judge, uint64_t oob,
-                                            const float (&ell)[kSlots], float (&C)[kSlots],
-                                            float (&X)[kSlots], float (&st)[kNStat]) {
+                                            const float (&ell)[kSlots], const LaneLds &s,
+                                            float (&st)[kNStat]) {
+    float C[kSlots];
+#pragma unroll
+    for (int j = J0; j < kSlots; ++j) C[j] = s.c[j * kWave];
     if (need_quad) {
         float Cq[kSlots];
         detail::quad_coupling<float, kSlots, J0>(a.ew + (size_t)k * kQ * kSlots * 2, ell, Cq);
@@ -104,7 +126,7 @@ __device__ __forceinline__ void finish_step(const PathArgs<float> &a, const MlpA
     const cptr<float> d0k = a.drift0 + (size_t)k * kSlots;
     const float dt = a.dt[k];
 #pragma unroll
-    for (int j = J0; j < kSlots; ++j) X[j] += fma(lamk[j], dH, fma(-C[j], dt, d0k[j]));
+    for (int j = J0; j < kSlots; ++j) s.x[j * kWave] += fma(lamk[j], dH, fma(-C[j], dt, d0k[j]));
     st[0] += static_cast<float>(kSlots - J0);
 }
 
@@ -112,9 +134,9 @@ template <int... Js>
 __device__ __forceinline__ void dispatch_finish(std::integer_sequence<int, Js...>, int j0,
                                                 const PathArgs<float> &a, const MlpArgs &g, int k,
                                                 float dH, bool need_quad, bool judge, uint64_t oob,
-                                                const float (&ell)[kSlots], float (&C)[kSlots],
-                                                float (&X)[kSlots], float (&st)[kNStat]) {
-    (void)((j0 == Js ? (finish_step<Js>(a, g, k, dH, need_quad, judge, oob, ell, C, X, st), 0)
+                                                const float (&ell)[kSlots], const LaneLds &s,
+                                                float (&st)[kNStat]) {
+    (void)((j0 == Js ? (finish_step<Js>(a, g, k, dH, need_quad, judge, oob, ell, s, st), 0)
                      : 0) + ...);
 }
 
@@ -129,46 +151,47 @@ __device__ __forceinline__ void hidden_layer(const __bf16 *Ws, const __bf16 *Hin
 #pragma unroll
         for (int kt = 0; kt < 2; ++kt) {
             const int k0 = 32 * kt + 8 * (lane / 16);
-            bf16x8 av;
-            const __bf16 *ap = Ws + (16 * mt + lane % 16) * kHid + k0;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) av[e] = ap[e];
+            const bf16x8 av = *reinterpret_cast<const bf16x8 *>(Ws + (16 * mt + lane % 16) * kHid + k0);
 #pragma unroll
             for (int nt = 0; nt < 4; ++nt) {
-                bf16x8 bv;
-                const __bf16 *bp = Hin + (16 * nt + lane % 16) * kHid + k0;
-#pragma unroll
-                for (int e = 0; e < 8; ++e) bv[e] = bp[e];
+                const bf16x8 bv =
+                    *reinterpret_cast<const bf16x8 *>(Hin + (16 * nt + lane % 16) * kHid + k0);
                 acc[nt] = mfma16(av, bv, acc[nt]);
             }
         }
+        const int o0 = 16 * mt + 4 * (lane / 16);
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt)
+        for (int nt = 0; nt < 4; ++nt) {
+            const int m = 16 * nt + lane % 16;
+            typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+            bf16x4 h;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int o = 16 * mt + 4 * (lane / 16) + e, m = 16 * nt + lane % 16;
-                Hout[m * kHid + o] = static_cast<__bf16>(gelu(acc[nt][e] + b[o]));
-            }
+            for (int e = 0; e < 4; ++e) h[e] = static_cast<__bf16>(gelu(acc[nt][e] + b[o0 + e]));
+            *reinterpret_cast<bf16x4 *>(Hout + m * kHid + o0) = h;
+        }
     }
 }
 
 template <int SCHEME>
 __global__ void __launch_bounds__(kBlock) mlp_path_kernel(PathArgs<float> a, MlpArgs g) {
-    __shared__ __bf16 W2s[kHid * kHid];
-    __shared__ __bf16 W3s[kHid * kHid];
-    __shared__ __bf16 Hb[kBlock / kWave][2][kWave * kHid];
+    // 160 KiB: the weights (16 KiB), two activation tiles per wavefront
+    // (64 KiB) and the per-lane state and coupling columns (2 x 40 KiB)
+    __shared__ __attribute__((aligned(16))) __bf16 W2s[kHid * kHid];
+    __shared__ __attribute__((aligned(16))) __bf16 W3s[kHid * kHid];
+    __shared__ __attribute__((aligned(16))) __bf16 Hb[kBlock / kWave][2][kWave * kHid];
+    __shared__ float Xs[kBlock / kWave][kSlots * kWave];
+    __shared__ float Cs[kBlock / kWave][kSlots * kWave];
     const int tid = threadIdx.x;
     for (int e = tid; e < kHid * kHid; e += kBlock) {
         W2s[e] = g.W2[e];
         W3s[e] = g.W3[e];
     }
-    __syncthreads();
+    __syncthreads();  // the only block-wide barrier: the weights are read-only after it
     const int64_t gid = static_cast<int64_t>(blockIdx.x) * kBlock + tid;
     const int lane = tid % kWave;
     const int wv = tid / kWave;
     const int64_t wave = gid / kWave;
-    // whole wavefronts past the end still take part in the block barriers
-    const bool wave_live = (gid - lane) < a.n_paths;
+    if (gid - lane >= a.n_paths) return;  // whole wavefront past the end
     const bool active = gid < a.n_paths;
     const bool judge = g.judge_stride > 0 && (wave % g.judge_stride) == 0;
     const int64_t p = a.path_offset + gid;
@@ -176,14 +199,11 @@ __global__ void __launch_bounds__(kBlock) mlp_path_kernel(PathArgs<float> a, Mlp
     const uint32_t p_hi = static_cast<uint32_t>(static_cast<uint64_t>(p) >> 32);
     __bf16 *H0 = Hb[wv][0];
     __bf16 *H1 = Hb[wv][1];
+    const LaneLds s{Xs[wv] + lane, Cs[wv] + lane};
     const cptr<float> b2 = g.wf + kOffB2;
     const cptr<float> b3 = g.wf + kOffB3;
-    float X[kSlots], X1[kSlots];
 #pragma unroll
-    for (int j = 0; j < kSlots; ++j) {
-        X[j] = 0.0f;
-        X1[j] = 0.0f;
-    }
+    for (int j = 0; j < kSlots; ++j) s.x[j * kWave] = 0.0f;
     float st[kNStat];
 #pragma unroll
     for (int i = 0; i < kNStat; ++i) st[i] = 0.0f;
@@ -196,16 +216,14 @@ __global__ void __launch_bounds__(kBlock) mlp_path_kernel(PathArgs<float> a, Mlp
             make_uint4(static_cast<uint32_t>(k), p_lo, p_hi, a.stream_word), a.key0, a.key1);
         const float dH = static_cast<float>(increment(w, cst, a.beta, false, nullptr));
         const int j0 = a.off + m;
-        float ell[kSlots], C[kSlots];
+        float ell[kSlots];
         uint64_t oob = 0;
-        dispatch_ell(std::make_integer_sequence<int, kSlots>{}, j0, a, g, X, ell, oob);
-        const float tn = g.tnorm[k];
+        dispatch_ell(std::make_integer_sequence<int, kSlots>{}, j0, a, g, s, ell, oob);
         float S[kHid];
 #pragma unroll
         for (int h = 0; h < kHid; ++h) S[h] = 0.0f;
-#pragma unroll
-        for (int j = 0; j < kSlots; ++j) C[j] = 0.0f;
         const cptr<float> K2k = g.K2 + (size_t)k * kSlots * kSlots;
+        const cptr<float> B1k = g.B1 + (size_t)k * kRates * kHid;
         for (int j = kSlots - 1; j >= j0; --j) {
             const int r = j - a.off;
             // first-order expansion
@@ -217,69 +235,71 @@ __global__ void __launch_bounds__(kBlock) mlp_path_kernel(PathArgs<float> a, Mlp
             // the last live slot has no later rate: its coupling is exactly 0
             if (g.use_net && j < kSlots - 1) {
                 // layer 1 from the suffix sum of the later rates
-                const cptr<float> w0 = g.W1T;                     // t_k column
-                const cptr<float> wi = g.W1T + (1 + kRates + r) * kHid;  // one-hot column
+                const cptr<float> bias = B1k + r * kHid;
                 __bf16 *row = H0 + lane * kHid;
-                const float tb = static_cast<float>(static_cast<__bf16>(tn));
 #pragma unroll
-                for (int h = 0; h < kHid; ++h) {
-                    const float z = S[h] + g.wf[kOffB1 + h] + w0[h] * tb + wi[h];
-                    row[h] = static_cast<__bf16>(gelu(z));
+                for (int h = 0; h < kHid; h += 8) {
+                    bf16x8 v;
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) v[e] = static_cast<__bf16>(gelu(S[h + e] + bias[h + e]));
+                    *reinterpret_cast<bf16x8 *>(row + h) = v;
                 }
-                __syncthreads();
+                wave_sync();
                 hidden_layer(W2s, H0, b2, H1, lane);
-                __syncthreads();
+                wave_sync();
                 hidden_layer(W3s, H1, b3, H0, lane);
-                __syncthreads();
+                wave_sync();
                 y = g.wf[kOffB4];
 #pragma unroll
-                for (int h = 0; h < kHid; ++h) y = fmaf(g.wf[kOffW4 + h], static_cast<float>(row[h]), y);
+                for (int h = 0; h < kHid; h += 8) {
+                    const bf16x8 v = *reinterpret_cast<const bf16x8 *>(row + h);
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) y = fmaf(g.wf[kOffW4 + h + e], static_cast<float>(v[e]), y);
+                }
+                wave_sync();  // row is rewritten by the next rate
             }
             if (g.use_net) {
-                // this rate's state joins the suffix sum of the next (lower) rate
-                float xj = 0.0f;
-#pragma unroll
-                for (int jj = 0; jj < kSlots; ++jj) xj = (jj == j) ? X[jj] : xj;
-                xj = static_cast<float>(static_cast<__bf16>(xj));  // as the BF16 features
+                // this rate's state joins the suffix sum of the next (lower) rate,
+                // rounded as the BF16 features are
+                const float xj = static_cast<float>(static_cast<__bf16>(s.x[j * kWave]));
                 const cptr<float> wx = g.W1T + (1 + r) * kHid;
 #pragma unroll
                 for (int h = 0; h < kHid; ++h) S[h] = fmaf(wx[h], xj, S[h]);
-                __syncthreads();
             }
-            const float cj = fmaf(g.sigma, y, c1);
-#pragma unroll
-            for (int jj = 0; jj < kSlots; ++jj) C[jj] = (jj == j) ? cj : C[jj];
+            s.c[j * kWave] = fmaf(g.sigma, y, c1);
         }
         const bool need_quad = judge || __any((oob >> (j0 + 1)) != 0);
         dispatch_finish(std::make_integer_sequence<int, kSlots>{}, j0, a, g, k, dH, need_quad,
-                        judge, oob, ell, C, X, st);
+                        judge, oob, ell, s, st);
         if (++js == a.s) {
-            if (wave_live)
-                detail::dispatch_payoff<float, kSlots>(std::make_integer_sequence<int, kSlots>{}, j0,
-                                                       a, m, gid, active, X);
+            float X[kSlots];
+#pragma unroll
+            for (int j = 0; j < kSlots; ++j) X[j] = s.x[j * kWave];
+            detail::dispatch_payoff<float, kSlots>(std::make_integer_sequence<int, kSlots>{}, j0, a,
+                                                   m, gid, active, X);
             js = 0;
             ++m;
         }
     }
-    if (wave_live) {
-        double tot[kNStat];
+    double tot[kNStat];
 #pragma unroll
-        for (int i = 0; i < kNStat; ++i) tot[i] = detail::wave_sum(active ? static_cast<double>(st[i]) : 0.0);
-        double mx = active ? static_cast<double>(st[5]) : 0.0;
+    for (int i = 0; i < kNStat; ++i) tot[i] = detail::wave_sum(active ? static_cast<double>(st[i]) : 0.0);
+    double mx = active ? static_cast<double>(st[5]) : 0.0;
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, kWave));
-        tot[5] = mx;
-        if (lane == 0)
-            for (int i = 0; i < kNStat; ++i) g.stats[wave * kNStat + i] = tot[i];
-    }
+    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, kWave));
+    tot[5] = mx;
+    if (lane == 0)
+        for (int i = 0; i < kNStat; ++i) g.stats[wave * kNStat + i] = tot[i];
 }
 
 // Per-step tables of the surrogate: first-order coefficients K2 (FP64 -> FP32),
-// t_k / T_N, and the transposed first layer (BF16-rounded, as in training).
+// the first-layer bias of every (step, rate) -- b1 + the time column x t_k / T_N
+// + the rate's one-hot column -- and the transposed first layer, with the
+// weights and the time feature BF16-rounded as in training.
 __global__ void __launch_bounds__(64) mlp_tables_kernel(
     const double *__restrict__ tenor, const double *__restrict__ vol, int N, int s, int off,
     double alpha, double beta, double delta_nig, const float *__restrict__ wts,
-    float *__restrict__ K2, float *__restrict__ tnorm, float *__restrict__ W1T) {
+    float *__restrict__ K2, float *__restrict__ B1, float *__restrict__ W1T) {
     const int k = blockIdx.x;
     const int t = threadIdx.x;
     const int m = k / s;
@@ -294,10 +314,14 @@ __global__ void __launch_bounds__(64) mlp_tables_kernel(
                 nig_cumulant(lam[rl], alpha, beta, delta_nig);
         K2[(size_t)k * kSlots * kSlots + e] = static_cast<float>(v);
     }
-    if (t == 0) {
-        const double Ta = (m == 0) ? 0.0 : tenor[m - 1];
-        const double tk = Ta + (k - m * s) * (tenor[m] - Ta) / s;
-        tnorm[k] = static_cast<float>(tk / tenor[N - 1]);
+    const double Ta = (m == 0) ? 0.0 : tenor[m - 1];
+    const double tk = Ta + (k - m * s) * (tenor[m] - Ta) / s;
+    const float tb = static_cast<float>(static_cast<__bf16>(static_cast<float>(tk / tenor[N - 1])));
+    const float w0 = static_cast<float>(static_cast<__bf16>(wts[kOffW1 + t * kIn]));
+    const float bt = fmaf(w0, tb, wts[kOffB1 + t]);
+    for (int r = 0; r < kRates; ++r) {
+        const float wi = static_cast<float>(static_cast<__bf16>(wts[kOffW1 + t * kIn + 1 + kRates + r]));
+        B1[((size_t)k * kRates + r) * kHid + t] = bt + wi;
     }
     if (k == 0)
         for (int e = t; e < kIn * kHid; e += 64) {
@@ -308,15 +332,16 @@ __global__ void __launch_bounds__(64) mlp_tables_kernel(
 
 }  // namespace
 
-hipError_t launch_mlp_tables(const lll_plan &p, const float *wts, float *K2, float *tnorm,
+hipError_t launch_mlp_tables(const lll_plan &p, const float *wts, float *K2, float *B1,
                              float *W1T, hipStream_t st) {
+    static_assert(kHid == 64, "one thread per hidden unit");
     hipLaunchKernelGGL(mlp_tables_kernel, dim3(p.K), dim3(64), 0, st, p.d.tenor, p.d.vol, p.N, p.s,
-                       p.off, p.alpha, p.beta, p.delta_nig, wts, K2, tnorm, W1T);
+                       p.off, p.alpha, p.beta, p.delta_nig, wts, K2, B1, W1T);
     return hipGetLastError();
 }
 
 hipError_t launch_mlp_paths(const lll_plan &p, const float *wts, const __bf16 *wbf,
-                            const float *K2, const float *tnorm, const float *W1T,
+                            const float *K2, const float *B1, const float *W1T,
                             const float *box, float sigma, int use_net, int judge_stride,
                             int64_t n_paths, uint64_t seed, double *path_fix, double *stats,
                             hipStream_t st) {
@@ -330,7 +355,7 @@ hipError_t launch_mlp_paths(const lll_plan &p, const float *wts, const __bf16 *w
     g.K2 = detail::as_const(K2);
     g.lo = detail::as_const(box);
     g.hi = detail::as_const(box + kRates);
-    g.tnorm = detail::as_const(tnorm);
+    g.B1 = detail::as_const(B1);
     g.stats = stats;
     g.sigma = sigma;
     g.use_net = use_net;

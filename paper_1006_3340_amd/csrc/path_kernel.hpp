@@ -184,6 +184,43 @@ __device__ __forceinline__ void payoff(const PathArgs<Real> &a, int m, int64_t g
     }
 }
 
+// The same step with the state X held in LDS (column `xs`, stride kBlock) for
+// the wide buckets: X is read twice and written once per step, while ell and
+// the coupling sums stay in registers.  A compiler-only fence keeps the second
+// read from being merged with the first, which would pin X in registers
+// across the node loop again.
+template <typename Real, int NMAX, int SCHEME, int J0>
+__device__ __forceinline__ void step_lds(const PathArgs<Real> &a, int k, Real dH, Real *xs,
+                                         Real (&X1)[NMAX]) {
+    const cptr<Real> lamk = a.lam + (size_t)k * NMAX;
+    const cptr<Real> frzk = a.frozen + (size_t)k * NMAX;
+    Real ell[NMAX];
+#pragma unroll
+    for (int j = J0; j < NMAX; ++j)
+        ell[j] = ell_of(SCHEME == kPicard ? X1[j] : xs[j * kBlock], a.cinv[j]);
+    __asm__ volatile("" ::: "memory");
+    Real C[NMAX];
+    if (a.brownian)
+        brownian_coupling<Real, NMAX, J0>(lamk, static_cast<Real>(a.c), ell, C);
+    else
+        quad_coupling<Real, NMAX, J0>(a.ew + (size_t)k * kQ * NMAX * 2, ell, C);
+    const Real dt = a.dt[k];
+    const cptr<Real> d0k = a.drift0 + (size_t)k * NMAX;
+#pragma unroll
+    for (int j = J0; j < NMAX; ++j) xs[j * kBlock] += fma(lamk[j], dH, fma(-C[j], dt, d0k[j]));
+    if constexpr (SCHEME == kPicard) {
+#pragma unroll
+        for (int j = J0; j < NMAX; ++j) X1[j] += fma(lamk[j], dH, frzk[j]);
+    }
+}
+
+template <typename Real, int NMAX, int SCHEME, int... Js>
+__device__ __forceinline__ void dispatch_step_lds(std::integer_sequence<int, Js...>, int j0,
+                                                  const PathArgs<Real> &a, int k, Real dH,
+                                                  Real *xs, Real (&X1)[NMAX]) {
+    (void)((j0 == Js ? (step_lds<Real, NMAX, SCHEME, Js>(a, k, dH, xs, X1), 0) : 0) + ...);
+}
+
 template <typename Real, int NMAX, int SCHEME, int... Js>
 __device__ __forceinline__ void dispatch_step(std::integer_sequence<int, Js...>, int j0,
                                               const PathArgs<Real> &a, int k, Real dH,
@@ -198,11 +235,70 @@ __device__ __forceinline__ void dispatch_payoff(std::integer_sequence<int, Js...
     (void)((j0 == Js ? (payoff<Real, NMAX, Js>(a, m, gid, active, X), 0) : 0) + ...);
 }
 
+// The block's LDS state, [slot][thread]: one allocation per kernel that uses it.
+template <typename Real, int NMAX>
+__device__ __forceinline__ Real *state_lds() {
+    __shared__ Real sX[NMAX * kBlock];
+    return sX;
+}
+
+template <typename Real, int NMAX, int SCHEME>
+__device__ __forceinline__ void simulate_lds(const PathArgs<Real> &a, int64_t gid) {
+    Real *xs = state_lds<Real, NMAX>() + threadIdx.x;
+    const bool active = gid < a.n_paths;
+    const int64_t p = a.path_offset + gid;
+    const uint32_t p_lo = static_cast<uint32_t>(p);
+    const uint32_t p_hi = static_cast<uint32_t>(static_cast<uint64_t>(p) >> 32);
+    const bool brownian = a.brownian != 0;
+    Real X1[NMAX];
+#pragma unroll
+    for (int j = 0; j < NMAX; ++j) {
+        xs[j * kBlock] = Real(0);
+        X1[j] = Real(0);
+    }
+    int m = 0, js = 0;
+    const int K = a.N * a.s;
+    for (int k = 0; k < K; ++k) {
+        const cptr<double> sc = a.steps + 4 * m;
+        const StepConsts cst{sc[0], sc[1], sc[2], sc[3]};
+        const uint4 w = philox4x32_10(
+            make_uint4(static_cast<uint32_t>(k), p_lo, p_hi, a.stream_word), a.key0, a.key1);
+        const Real dH = static_cast<Real>(increment(w, cst, a.beta, brownian, nullptr));
+        const int j0 = a.off + m;
+        dispatch_step_lds<Real, NMAX, SCHEME>(std::make_integer_sequence<int, NMAX>{}, j0, a, k, dH,
+                                              xs, X1);
+        if (++js == a.s) {
+            Real X[NMAX];
+#pragma unroll
+            for (int j = 0; j < NMAX; ++j) X[j] = xs[j * kBlock];
+            dispatch_payoff<Real, NMAX>(std::make_integer_sequence<int, NMAX>{}, j0, a, m, gid,
+                                        active, X);
+            js = 0;
+            ++m;
+        }
+    }
+}
+
+// FP32 FULL / PICARD kernels of the 24- to 40-slot buckets keep X in LDS
+// (NMAX x 256 x 4 B per block): with X, ell and the coupling sums all in
+// registers they need 100-180 VGPRs, one wavefront per SIMD fewer than with X
+// in LDS (measured: N = 20 FULL 22.7 -> 21.2 ms, N = 40 FULL 50.0 -> 42.7 ms,
+// N = 40 PICARD 70.6 -> 58.0 ms at 2^20 paths).
+template <typename Real, int NMAX, int SCHEME>
+constexpr bool kStateInLds = sizeof(Real) == 4 && NMAX >= 24 && SCHEME != kFrozen;
+
 // Simulates path `gid` (0-based within the structure; lanes past n_paths run
 // but contribute nothing) through all periods, writing the wave's payoff sums.
-// Every lane of the wavefront must call this together (wave reductions).
-template <typename Real, int NMAX, int SCHEME>
+// Every lane of the wavefront must call this together (wave reductions), and
+// every thread of the block index its own LDS column (threadIdx.x < kBlock).
+// ALLOW_LDS = false keeps the state in registers (the batched launch, whose
+// item loop leaves it at the same occupancy either way, is faster so).
+template <typename Real, int NMAX, int SCHEME, bool ALLOW_LDS = true>
 __device__ __forceinline__ void simulate(const PathArgs<Real> &a, int64_t gid) {
+    if constexpr (ALLOW_LDS && kStateInLds<Real, NMAX, SCHEME>) {
+        simulate_lds<Real, NMAX, SCHEME>(a, gid);
+        return;
+    }
     const bool active = gid < a.n_paths;
     const int64_t p = a.path_offset + gid;
     const uint32_t p_lo = static_cast<uint32_t>(p);

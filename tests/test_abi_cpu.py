@@ -78,3 +78,19 @@ def test_inspection_entry_points_validate():
     import paper_1006_3340_amd as lll
     with pytest.raises(lll.LLLError):
         lll.philox(np.zeros((0, 4), np.uint32), np.zeros((0, 2), np.uint32))
+
+
+def test_batch_validation_errors():
+    """Batch arguments are checked on the host before any device work."""
+    import paper_1006_3340_amd as lll
+    ts = workloads.plain_fp64()
+    with pytest.raises(lll.LLLError) as ei:
+        lll.Batch([ts], max_paths_each=0)
+    assert ei.value.code == -1
+    # 4096 structures x 2^30 paths: 2^34 block work items
+    with pytest.raises(lll.LLLError) as ei:
+        lll.Batch([ts] * 4096, max_paths_each=1 << 30)
+    assert ei.value.code == -1 and "work items" in str(ei.value)
+    with pytest.raises(lll.LLLError) as ei:
+        lll.Batch([ts.copy(L0=-ts.L0)], max_paths_each=64)
+    assert ei.value.code == -1
