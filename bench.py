@@ -123,11 +123,13 @@ PEAK_BF16 = 2.5e15     # MI355X dense BF16 matrix cores, FLOP/s
 
 def mlp_flops_per_rate_step(n_later: int) -> dict:
     """Algorithmic flops of the surrogate coupling of one rate with n_later later
-    rates (FMA = 2): matrix cores 2 x 64x64 layers x 64-wide FMA; vector ALU the
-    first-order expansion (2 per later rate), the first layer's suffix update
-    and pre-activation (6 per unit), three GELU layers (12 per unit), the
-    output dot (128) and the hidden biases (128)."""
-    return {"mfma": 2 * 2 * 64 * 64, "valu": 2 * n_later + 6 * 64 + 3 * 12 * 64 + 128 + 128}
+    rates (FMA = 2): on the matrix cores the first layer over the later rates'
+    states (2 x 64 x n_later; the time and one-hot inputs are a bias table) and
+    the two 64x64 hidden layers; on the vector ALU the first-order expansion
+    (2 per later rate), three 64-wide GELU layers (8 per unit) and the output
+    dot (128)."""
+    return {"mfma": 2 * 64 * n_later + 2 * 2 * 64 * 64,
+            "valu": 2 * n_later + 3 * 8 * 64 + 128}
 
 
 def bench_mlp(lll, stream, n: int = 1 << 20, train_steps: int = 3000) -> dict:
@@ -172,7 +174,7 @@ def bench_mlp(lll, stream, n: int = 1 << 20, train_steps: int = 3000) -> dict:
     s, N = ts.steps_per_period, ts.n_rates
     mf = va = 0
     for m in range(N):
-        for i in range(m, N):
+        for i in range(m, N - 1):      # the last rate has no coupling
             f = mlp_flops_per_rate_step(N - 1 - i)
             mf += s * f["mfma"]
             va += s * f["valu"]

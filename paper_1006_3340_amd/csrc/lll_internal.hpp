@@ -48,7 +48,7 @@ struct DeviceTables {
 
 namespace lll {
 struct MlpBuffers {
-    float *K2 = nullptr, *B1 = nullptr, *W1T = nullptr, *open_box = nullptr;
+    float *K2 = nullptr, *B1 = nullptr, *open_box = nullptr;
     void *zero_params = nullptr;  // zero FP32 + BF16 parameter vectors (first-order runs)
     double *stats = nullptr;
     int64_t stat_waves = 0;

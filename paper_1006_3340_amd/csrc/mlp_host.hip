@@ -30,12 +30,11 @@ hipError_t launch_tiles(const __bf16 *feat, const float *target, const int *idx,
 hipError_t launch_batch_index(int *idx, int B, int64_t n_pairs, uint32_t step, uint64_t seed,
                               hipStream_t st);
 hipError_t launch_mlp_tables(const lll_plan &p, const float *wts, float *K2, float *B1,
-                             float *W1T, hipStream_t st);
+                             hipStream_t st);
 hipError_t launch_mlp_paths(const lll_plan &p, const float *wts, const __bf16 *wbf,
-                            const float *K2, const float *B1, const float *W1T,
-                            const float *box, float sigma, int use_net, int judge_stride,
-                            int64_t n_paths, uint64_t seed, double *path_fix, double *stats,
-                            hipStream_t st);
+                            const float *K2, const float *B1, const float *box, float sigma,
+                            int use_net, int judge_stride, int64_t n_paths, uint64_t seed,
+                            double *path_fix, double *stats, hipStream_t st);
 
 namespace {
 __global__ void to_bf16_kernel(const float *__restrict__ in, __bf16 *__restrict__ out, int64_t n) {
@@ -47,7 +46,7 @@ __global__ void to_bf16_kernel(const float *__restrict__ in, __bf16 *__restrict_
 
 void mlp_plan_free(lll_plan &p) {
     MlpBuffers &b = p.mb;
-    void *ptrs[] = {b.K2, b.B1, b.W1T, b.open_box, b.stats, b.zero_params};
+    void *ptrs[] = {b.K2, b.B1, b.open_box, b.stats, b.zero_params};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     p.mb = MlpBuffers{};
@@ -392,7 +391,6 @@ int lll_plan_execute_mlp(lll_plan *plan, const lll_mlp *m, int use_net, int64_t 
     if (!b.K2) {
         e = hipMalloc(&b.K2, sizeof(float) * (size_t)plan->K * kRates * kRates);
         if (e == hipSuccess) e = hipMalloc(&b.B1, sizeof(float) * (size_t)plan->K * kRates * kHid);
-        if (e == hipSuccess) e = hipMalloc(&b.W1T, sizeof(float) * kIn * kHid);
         if (e == hipSuccess) e = hipMalloc(&b.open_box, sizeof(float) * 2 * kRates);
         if (e == hipSuccess) e = hipMalloc(&b.stats, sizeof(double) * plan->max_waves * 8);
         const size_t zbytes = (sizeof(float) + sizeof(__bf16)) * kParams;
@@ -421,12 +419,12 @@ int lll_plan_execute_mlp(lll_plan *plan, const lll_mlp *m, int use_net, int64_t 
     const bool t = plan->timing;
     e = t ? hipEventRecord(plan->ev[0], st) : hipSuccess;
     if (e == hipSuccess) e = lll::launch_precompute(*plan, st);
-    if (e == hipSuccess) e = launch_mlp_tables(*plan, wts, b.K2, b.B1, b.W1T, st);
+    if (e == hipSuccess) e = launch_mlp_tables(*plan, wts, b.K2, b.B1, st);
     const float *box = use_net ? m->info : b.open_box;
     const float sigma = use_net ? m->info_host[2 * kRates] : 0.0f;
     if (e == hipSuccess && t) e = hipEventRecord(plan->ev[1], st);
     if (e == hipSuccess)
-        e = launch_mlp_paths(*plan, wts, wbf, b.K2, b.B1, b.W1T, box, sigma, use_net,
+        e = launch_mlp_paths(*plan, wts, wbf, b.K2, b.B1, box, sigma, use_net,
                              judge_stride, n_paths, seed, path_fix_dev, b.stats, st);
     if (e == hipSuccess && t) e = hipEventRecord(plan->ev[2], st);
     if (e == hipSuccess) e = lll::launch_reduce(*plan, n_paths, st);

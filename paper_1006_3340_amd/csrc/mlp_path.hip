@@ -7,16 +7,19 @@
 // - kappa(lambda_i) - kappa(lambda_l) (paper Section 3.2, eq. (drifta)).  With
 // use_net = 0 the kernel runs the first-order drift expansion alone.
 //
-// The network's first layer is a suffix sum over the rates (the features of
-// rate i are the states of the rates l > i), so it costs 64 FMAs per rate plus
-// one add of a per-(step, rate) bias table (b1 + the time and one-hot
-// columns); the two hidden 64x64 layers run on the matrix cores for the
-// wave's 64 paths at once: Z^T = W . H^T with W from LDS (shared by the
-// block) and H staged per wave in LDS, v_mfma_f32_16x16x32_bf16, FP32
-// accumulation.  The state X and the couplings C live in LDS columns (one per
-// thread), so a rate's state and coupling are addressed by the loop index
-// without register selects.  Nothing is shared between wavefronts inside the
-// step loop, so the waves synchronise only with themselves.
+// All three layers run on the matrix cores (v_mfma_f32_16x16x32_bf16, FP32
+// accumulation) for the wavefront's 64 paths at once, as Z^T = W . H^T: the
+// weights are the A operand (LDS, shared by the block), the activations the B
+// operand, the accumulators start from the biases.  Layer 1 reads the BF16
+// state of all rates from a per-wavefront LDS tile written once per step and
+// masks the rates l <= i of rate i's features as it loads them (its bias,
+// b1 + the time column x t_k/T_N + rate i's one-hot column, is a per-(step,
+// rate) table).  A lane's accumulator tile holds units 16 mt + 4 g + e of
+// paths 16 nt + c (lane = 16 g + c); with the hidden units of the next layer's
+// K dimension permuted accordingly (perm_unit), those GELU outputs are
+// already that layer's B operand, so the hidden activations never leave the
+// registers.  The output unit reduces the 16 units per lane across the four
+// lane groups.  Nothing is shared between wavefronts inside the step loop.
 //
 // Fallback: a path whose later-rate state leaves the range seen in training
 // (per rate) takes the 64-node quadrature coupling for that rate instead.
@@ -41,72 +44,81 @@ using detail::PathArgs;
 
 constexpr int kSlots = kRates;  // the surrogate runs in the 40-slot bucket
 constexpr int kNStat = 8;
+constexpr int kLd = 72;         // padded row length (BF16) of the LDS tiles
+
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 struct MlpArgs {
-    cptr<float> W1T;    // [96][64] first layer, transposed (BF16-rounded values)
     cptr<float> wf;     // FP32 parameter vector (biases, w4, b4)
-    const __bf16 *W2;   // [64][64]
-    const __bf16 *W3;   // [64][64]
+    const float *wfv;   // the same, for per-lane loads
+    const __bf16 *wbf;  // BF16 parameter vector
     cptr<float> K2;     // [K][40][40]
     cptr<float> lo;     // [40] trust box per slot
     cptr<float> hi;
-    cptr<float> B1;     // [K][40][64] first-layer bias of (step, rate)
+    const float *B1;    // [K][40][64] first-layer bias of (step, rate)
     double *stats;      // [waves][kNStat]
     float sigma;
     int use_net;
     int judge_stride;
 };
 
-// LDS of one wavefront's LDS-resident per-lane state: column `lane` of
-// [slot][kWave] arrays.
-struct LaneLds {
-    float *x;  // X_j at x[j * kWave]
-    float *c;  // C_j at c[j * kWave]
-};
+// Hidden unit behind K slot ks of a hidden layer's input: slot (kt, g, e) of
+// lane group g holds the unit that group's accumulators produced for row
+// tile mt = 2 kt + e / 4, element e % 4.
+__host__ __device__ constexpr int perm_unit(int ks) {
+    return 16 * (2 * (ks / 32) + (ks % 8) / 4) + 4 * ((ks % 32) / 8) + ks % 4;
+}
 
-// Orders this wavefront's LDS accesses across lanes (all LDS data used inside
-// the step loop is private to the wavefront).
+// Orders this wavefront's LDS accesses across its lanes.
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Start of a step for the live slots J0..: the trust-box test of the state and
+// the first-order couplings C_j = sum_{l>j} ell_l K2_{k,j,l} of every live rate.
 template <int J0>
-__device__ __forceinline__ void ell_and_box(const PathArgs<float> &a, const MlpArgs &g,
-                                            const LaneLds &s, float (&ell)[kSlots], uint64_t &oob) {
+__device__ __forceinline__ void first_order(const PathArgs<float> &a, const MlpArgs &g, int k,
+                                            const float (&X)[kSlots], float (&C)[kSlots],
+                                            uint64_t &oob) {
+    float ell[kSlots];
     oob = 0;
 #pragma unroll
-    for (int j = 0; j < kSlots; ++j) {
-        if (j >= J0) {
-            const float x = s.x[j * kWave];
-            ell[j] = detail::ell_of(x, a.cinv[j]);
-            const bool out = (x < g.lo[j]) || (x > g.hi[j]);
-            oob |= static_cast<uint64_t>(out) << j;
-        } else {
-            ell[j] = 0.0f;
-        }
+    for (int j = J0; j < kSlots; ++j) {
+        ell[j] = detail::ell_of(X[j], a.cinv[j]);
+        const bool out = (X[j] < g.lo[j]) || (X[j] > g.hi[j]);
+        oob |= static_cast<uint64_t>(out) << j;
+    }
+    const cptr<float> K2k = g.K2 + (size_t)k * kSlots * kSlots;
+#pragma unroll
+    for (int j = J0; j < kSlots; ++j) {
+        float c1 = 0.0f;
+#pragma unroll
+        for (int l = j + 1; l < kSlots; ++l) c1 = fmaf(ell[l], K2k[j * kSlots + l], c1);
+        C[j] = c1;
     }
 }
 
 template <int... Js>
-__device__ __forceinline__ void dispatch_ell(std::integer_sequence<int, Js...>, int j0,
-                                             const PathArgs<float> &a, const MlpArgs &g,
-                                             const LaneLds &s, float (&ell)[kSlots], uint64_t &oob) {
-    (void)((j0 == Js ? (ell_and_box<Js>(a, g, s, ell, oob), 0) : 0) + ...);
+__device__ __forceinline__ void dispatch_first_order(std::integer_sequence<int, Js...>, int j0,
+                                                     const PathArgs<float> &a, const MlpArgs &g,
+                                                     int k, const float (&X)[kSlots],
+                                                     float (&C)[kSlots], uint64_t &oob) {
+    (void)((j0 == Js ? (first_order<Js>(a, g, k, X, C, oob), 0) : 0) + ...);
 }
 
-// Quadrature coupling for the judge and the fallback, plus the state update.
+// Quadrature coupling for the judge and the fallback (ell recomputed from the
+// state, which this step has not changed yet), then the state update.
 template <int J0>
-__device__ __forceinline__ void finish_step(const PathArgs<float> &a, const MlpArgs &g, int k,
-                                            float dH, bool need_quad, bool judge, uint64_t oob,
-                                            const float (&ell)[kSlots], const LaneLds &s,
+__device__ __forceinline__ void finish_step(const PathArgs<float> &a, int k, float dH,
+                                            bool need_quad, bool judge, uint64_t oob,
+                                            float (&C)[kSlots], float (&X)[kSlots],
                                             float (&st)[kNStat]) {
-    float C[kSlots];
-#pragma unroll
-    for (int j = J0; j < kSlots; ++j) C[j] = s.c[j * kWave];
     if (need_quad) {
-        float Cq[kSlots];
+        float ell[kSlots], Cq[kSlots];
+#pragma unroll
+        for (int j = J0; j < kSlots; ++j) ell[j] = detail::ell_of(X[j], a.cinv[j]);
         detail::quad_coupling<float, kSlots, J0>(a.ew + (size_t)k * kQ * kSlots * 2, ell, Cq);
 #pragma unroll
         for (int j = J0; j < kSlots; ++j) {
@@ -126,70 +138,78 @@ __device__ __forceinline__ void finish_step(const PathArgs<float> &a, const MlpA
     const cptr<float> d0k = a.drift0 + (size_t)k * kSlots;
     const float dt = a.dt[k];
 #pragma unroll
-    for (int j = J0; j < kSlots; ++j) s.x[j * kWave] += fma(lamk[j], dH, fma(-C[j], dt, d0k[j]));
+    for (int j = J0; j < kSlots; ++j) X[j] += fma(lamk[j], dH, fma(-C[j], dt, d0k[j]));
     st[0] += static_cast<float>(kSlots - J0);
 }
 
 template <int... Js>
 __device__ __forceinline__ void dispatch_finish(std::integer_sequence<int, Js...>, int j0,
-                                                const PathArgs<float> &a, const MlpArgs &g, int k,
-                                                float dH, bool need_quad, bool judge, uint64_t oob,
-                                                const float (&ell)[kSlots], const LaneLds &s,
+                                                const PathArgs<float> &a, int k, float dH,
+                                                bool need_quad, bool judge, uint64_t oob,
+                                                float (&C)[kSlots], float (&X)[kSlots],
                                                 float (&st)[kNStat]) {
-    (void)((j0 == Js ? (finish_step<Js>(a, g, k, dH, need_quad, judge, oob, ell, s, st), 0)
-                     : 0) + ...);
+    (void)((j0 == Js ? (finish_step<Js>(a, k, dH, need_quad, judge, oob, C, X, st), 0) : 0) + ...);
 }
 
-// One hidden 64x64 layer for the wave's 64 paths: Hout[m][o] = gelu(sum_k W[o][k] Hin[m][k] + b[o]).
-__device__ __forceinline__ void hidden_layer(const __bf16 *Ws, const __bf16 *Hin, cptr<float> b,
-                                             __bf16 *Hout, int lane) {
-#pragma unroll 1
-    for (int mt = 0; mt < 4; ++mt) {
-        floatx4 acc[4];
+// acc[mt] = the biases of this lane's units 16 mt + 4 grp + e (reloaded at
+// every use, see layer2).
+__device__ __forceinline__ void bias_init(const float *b, int grp, floatx4 (&acc)[4]) {
+    __asm__ volatile("" ::: "memory");
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) acc[nt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int mt = 0; mt < 4; ++mt) acc[mt] = *reinterpret_cast<const floatx4 *>(b + 16 * mt + 4 * grp);
+}
+
+// B operands of the next layer from a finished accumulator tile: GELU, BF16,
+// K slots (kt, grp, e) = units of row tiles 2 kt and 2 kt + 1.
+__device__ __forceinline__ void activate(const floatx4 (&acc)[4], bf16x8 (&h)[2]) {
 #pragma unroll
-        for (int kt = 0; kt < 2; ++kt) {
-            const int k0 = 32 * kt + 8 * (lane / 16);
-            const bf16x8 av = *reinterpret_cast<const bf16x8 *>(Ws + (16 * mt + lane % 16) * kHid + k0);
+    for (int kt = 0; kt < 2; ++kt)
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) {
-                const bf16x8 bv =
-                    *reinterpret_cast<const bf16x8 *>(Hin + (16 * nt + lane % 16) * kHid + k0);
-                acc[nt] = mfma16(av, bv, acc[nt]);
-            }
+        for (int e = 0; e < 4; ++e) {
+            h[kt][e] = static_cast<__bf16>(gelu(acc[2 * kt][e]));
+            h[kt][4 + e] = static_cast<__bf16>(gelu(acc[2 * kt + 1][e]));
         }
-        const int o0 = 16 * mt + 4 * (lane / 16);
+}
+
+// One layer for two column tiles (32 paths): acc[t][mt] += W[mt rows] . B[t].
+// The weight fragments are read from LDS at every use: the compiler-only
+// memory fence keeps them from being hoisted out of the rate loop, where the
+// three layers' fragments would pin 96 registers.
+__device__ __forceinline__ void layer2(const __bf16 *Wp, int lane, const bf16x8 (&B)[2][2],
+                                       floatx4 (&acc)[2][4]) {
+    __asm__ volatile("" ::: "memory");
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-            const int m = 16 * nt + lane % 16;
-            typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-            bf16x4 h;
+    for (int kt = 0; kt < 2; ++kt)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) h[e] = static_cast<__bf16>(gelu(acc[nt][e] + b[o0 + e]));
-            *reinterpret_cast<bf16x4 *>(Hout + m * kHid + o0) = h;
+        for (int mt = 0; mt < 4; ++mt) {
+            const bf16x8 w = *reinterpret_cast<const bf16x8 *>(
+                Wp + (16 * mt + lane % 16) * kLd + 32 * kt + 8 * (lane / 16));
+#pragma unroll
+            for (int t = 0; t < 2; ++t) acc[t][mt] = mfma16(w, B[t][kt], acc[t][mt]);
         }
-    }
 }
 
 template <int SCHEME>
 __global__ void __launch_bounds__(kBlock) mlp_path_kernel(PathArgs<float> a, MlpArgs g) {
-    // 160 KiB: the weights (16 KiB), two activation tiles per wavefront
-    // (64 KiB) and the per-lane state and coupling columns (2 x 40 KiB)
-    __shared__ __attribute__((aligned(16))) __bf16 W2s[kHid * kHid];
-    __shared__ __attribute__((aligned(16))) __bf16 W3s[kHid * kHid];
-    __shared__ __attribute__((aligned(16))) __bf16 Hb[kBlock / kWave][2][kWave * kHid];
-    __shared__ float Xs[kBlock / kWave][kSlots * kWave];
-    __shared__ float Cs[kBlock / kWave][kSlots * kWave];
+    // 63 KiB: three padded weight tiles (shared) and one state tile per wavefront
+    __shared__ __attribute__((aligned(16))) __bf16 W1p[kHid * kLd];
+    __shared__ __attribute__((aligned(16))) __bf16 W2p[kHid * kLd];
+    __shared__ __attribute__((aligned(16))) __bf16 W3p[kHid * kLd];
+    __shared__ __attribute__((aligned(16))) __bf16 Ft[kBlock / kWave][kWave * kLd];
     const int tid = threadIdx.x;
-    for (int e = tid; e < kHid * kHid; e += kBlock) {
-        W2s[e] = g.W2[e];
-        W3s[e] = g.W3[e];
+    for (int e = tid; e < kHid * kLd; e += kBlock) {
+        const int o = e / kLd, ks = e % kLd;
+        const __bf16 z = static_cast<__bf16>(0.0f);
+        // layer 1's K slots are register slots: slot ks holds rate ks - off
+        const int rate = ks - a.off;
+        W1p[e] = (ks < kSlots && rate >= 0) ? g.wbf[kOffW1 + o * kIn + 1 + rate] : z;
+        W2p[e] = (ks < kHid) ? g.wbf[kOffW2 + o * kHid + perm_unit(ks)] : z;
+        W3p[e] = (ks < kHid) ? g.wbf[kOffW3 + o * kHid + perm_unit(ks)] : z;
     }
     __syncthreads();  // the only block-wide barrier: the weights are read-only after it
     const int64_t gid = static_cast<int64_t>(blockIdx.x) * kBlock + tid;
     const int lane = tid % kWave;
-    const int wv = tid / kWave;
+    const int grp = lane / 16;
     const int64_t wave = gid / kWave;
     if (gid - lane >= a.n_paths) return;  // whole wavefront past the end
     const bool active = gid < a.n_paths;
@@ -197,13 +217,10 @@ __global__ void __launch_bounds__(kBlock) mlp_path_kernel(PathArgs<float> a, Mlp
     const int64_t p = a.path_offset + gid;
     const uint32_t p_lo = static_cast<uint32_t>(p);
     const uint32_t p_hi = static_cast<uint32_t>(static_cast<uint64_t>(p) >> 32);
-    __bf16 *H0 = Hb[wv][0];
-    __bf16 *H1 = Hb[wv][1];
-    const LaneLds s{Xs[wv] + lane, Cs[wv] + lane};
-    const cptr<float> b2 = g.wf + kOffB2;
-    const cptr<float> b3 = g.wf + kOffB3;
+    __bf16 *F = Ft[tid / kWave];
+    float X[kSlots];
 #pragma unroll
-    for (int j = 0; j < kSlots; ++j) s.x[j * kWave] = 0.0f;
+    for (int j = 0; j < kSlots; ++j) X[j] = 0.0f;
     float st[kNStat];
 #pragma unroll
     for (int i = 0; i < kNStat; ++i) st[i] = 0.0f;
@@ -216,65 +233,101 @@ __global__ void __launch_bounds__(kBlock) mlp_path_kernel(PathArgs<float> a, Mlp
             make_uint4(static_cast<uint32_t>(k), p_lo, p_hi, a.stream_word), a.key0, a.key1);
         const float dH = static_cast<float>(increment(w, cst, a.beta, false, nullptr));
         const int j0 = a.off + m;
-        float ell[kSlots];
+        float C[kSlots];
         uint64_t oob = 0;
-        dispatch_ell(std::make_integer_sequence<int, kSlots>{}, j0, a, g, s, ell, oob);
-        float S[kHid];
+        dispatch_first_order(std::make_integer_sequence<int, kSlots>{}, j0, a, g, k, X, C, oob);
+        // the last live slot has no later rate: its coupling stays exactly 0
+        if (g.use_net && j0 < kSlots - 1) {
+            // this lane's row of the state tile: BF16 X of slot j at column j
+            wave_sync();  // the previous step's reads of the tile are done
 #pragma unroll
-        for (int h = 0; h < kHid; ++h) S[h] = 0.0f;
-        const cptr<float> K2k = g.K2 + (size_t)k * kSlots * kSlots;
-        const cptr<float> B1k = g.B1 + (size_t)k * kRates * kHid;
-        for (int j = kSlots - 1; j >= j0; --j) {
-            const int r = j - a.off;
-            // first-order expansion
-            float c1 = 0.0f;
-            const cptr<float> K2row = K2k + j * kSlots;
+            for (int c0 = 0; c0 < kSlots; c0 += 8) {
+                bf16x8 v;
 #pragma unroll
-            for (int jj = 0; jj < kSlots; ++jj) c1 = fmaf(ell[jj], K2row[jj], c1);
-            float y = 0.0f;
-            // the last live slot has no later rate: its coupling is exactly 0
-            if (g.use_net && j < kSlots - 1) {
-                // layer 1 from the suffix sum of the later rates
-                const cptr<float> bias = B1k + r * kHid;
-                __bf16 *row = H0 + lane * kHid;
-#pragma unroll
-                for (int h = 0; h < kHid; h += 8) {
-                    bf16x8 v;
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) v[e] = static_cast<__bf16>(gelu(S[h + e] + bias[h + e]));
-                    *reinterpret_cast<bf16x8 *>(row + h) = v;
-                }
-                wave_sync();
-                hidden_layer(W2s, H0, b2, H1, lane);
-                wave_sync();
-                hidden_layer(W3s, H1, b3, H0, lane);
-                wave_sync();
-                y = g.wf[kOffB4];
-#pragma unroll
-                for (int h = 0; h < kHid; h += 8) {
-                    const bf16x8 v = *reinterpret_cast<const bf16x8 *>(row + h);
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) y = fmaf(g.wf[kOffW4 + h + e], static_cast<float>(v[e]), y);
-                }
-                wave_sync();  // row is rewritten by the next rate
+                for (int e = 0; e < 8; ++e) v[e] = static_cast<__bf16>(X[c0 + e]);
+                *reinterpret_cast<bf16x8 *>(F + lane * kLd + c0) = v;
             }
-            if (g.use_net) {
-                // this rate's state joins the suffix sum of the next (lower) rate,
-                // rounded as the BF16 features are
-                const float xj = static_cast<float>(static_cast<__bf16>(s.x[j * kWave]));
-                const cptr<float> wx = g.W1T + (1 + r) * kHid;
+            *reinterpret_cast<bf16x8 *>(F + lane * kLd + 40) = bf16x8{};
+            *reinterpret_cast<bf16x8 *>(F + lane * kLd + 48) = bf16x8{};
+            *reinterpret_cast<bf16x8 *>(F + lane * kLd + 56) = bf16x8{};
+            wave_sync();
+            const float *B1k = g.B1 + (size_t)k * kRates * kHid;
+            for (int j = kSlots - 2; j >= j0; --j) {
+                const int r = j - a.off;
+                // features of the rate in slot j: state columns l > j (dword d
+                // of K slice kt holds columns 32 kt + 8 grp + 2 d and + 1)
+                uint32_t mask[2][4];
 #pragma unroll
-                for (int h = 0; h < kHid; ++h) S[h] = fmaf(wx[h], xj, S[h]);
+                for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) {
+                        const int l0 = 32 * kt + 8 * grp + 2 * d;
+                        mask[kt][d] = (l0 > j ? 0x0000FFFFu : 0u) | (l0 + 1 > j ? 0xFFFF0000u : 0u);
+                    }
+                float part[4];
+#pragma unroll 1
+                for (int np = 0; np < 2; ++np) {
+                    bf16x8 B[2][2];
+                    floatx4 acc[2][4];
+#pragma unroll
+                    for (int t = 0; t < 2; ++t) {
+                        const int nt = 2 * np + t;
+#pragma unroll
+                        for (int kt = 0; kt < 2; ++kt) {
+                            bf16x8 f = *reinterpret_cast<const bf16x8 *>(
+                                F + (16 * nt + lane % 16) * kLd + 32 * kt + 8 * grp);
+                            uint32_t *u = reinterpret_cast<uint32_t *>(&f);
+#pragma unroll
+                            for (int d = 0; d < 4; ++d) u[d] &= mask[kt][d];
+                            B[t][kt] = f;
+                        }
+                        bias_init(B1k + r * kHid, grp, acc[t]);
+                    }
+                    layer2(W1p, lane, B, acc);
+#pragma unroll
+                    for (int t = 0; t < 2; ++t) {
+                        activate(acc[t], B[t]);
+                        bias_init(g.wfv + kOffB2, grp, acc[t]);
+                    }
+                    layer2(W2p, lane, B, acc);
+#pragma unroll
+                    for (int t = 0; t < 2; ++t) {
+                        activate(acc[t], B[t]);
+                        bias_init(g.wfv + kOffB3, grp, acc[t]);
+                    }
+                    layer2(W3p, lane, B, acc);
+                    // output unit: this lane's 16 units of its column tile
+                    __asm__ volatile("" ::: "memory");
+#pragma unroll
+                    for (int t = 0; t < 2; ++t) {
+                        float sum = 0.0f;
+#pragma unroll
+                        for (int mt = 0; mt < 4; ++mt) {
+                            const floatx4 w4 =
+                                *reinterpret_cast<const floatx4 *>(g.wfv + kOffW4 + 16 * mt + 4 * grp);
+#pragma unroll
+                            for (int e = 0; e < 4; ++e)
+                                sum = fmaf(w4[e], static_cast<float>(static_cast<__bf16>(gelu(acc[t][mt][e]))), sum);
+                        }
+                        part[2 * np + t] = sum;
+                    }
+                }
+                // sum over the four lane groups; lane 16 grp + c keeps column tile grp
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt) {
+                    part[nt] += __shfl_xor(part[nt], 16, kWave);
+                    part[nt] += __shfl_xor(part[nt], 32, kWave);
+                }
+                const float mine = grp == 0 ? part[0] : grp == 1 ? part[1] : grp == 2 ? part[2] : part[3];
+                const float sy = g.sigma * (g.wf[kOffB4] + mine);
+#pragma unroll
+                for (int jj = 0; jj < kSlots - 1; ++jj) C[jj] += (jj == j) ? sy : 0.0f;
             }
-            s.c[j * kWave] = fmaf(g.sigma, y, c1);
         }
         const bool need_quad = judge || __any((oob >> (j0 + 1)) != 0);
-        dispatch_finish(std::make_integer_sequence<int, kSlots>{}, j0, a, g, k, dH, need_quad,
-                        judge, oob, ell, s, st);
+        dispatch_finish(std::make_integer_sequence<int, kSlots>{}, j0, a, k, dH, need_quad, judge,
+                        oob, C, X, st);
         if (++js == a.s) {
-            float X[kSlots];
-#pragma unroll
-            for (int j = 0; j < kSlots; ++j) X[j] = s.x[j * kWave];
             detail::dispatch_payoff<float, kSlots>(std::make_integer_sequence<int, kSlots>{}, j0, a,
                                                    m, gid, active, X);
             js = 0;
@@ -292,14 +345,14 @@ __global__ void __launch_bounds__(kBlock) mlp_path_kernel(PathArgs<float> a, Mlp
         for (int i = 0; i < kNStat; ++i) g.stats[wave * kNStat + i] = tot[i];
 }
 
-// Per-step tables of the surrogate: first-order coefficients K2 (FP64 -> FP32),
-// the first-layer bias of every (step, rate) -- b1 + the time column x t_k / T_N
-// + the rate's one-hot column -- and the transposed first layer, with the
-// weights and the time feature BF16-rounded as in training.
+// Per-step tables of the surrogate: first-order coefficients K2 (FP64 -> FP32)
+// and the first-layer bias of every (step, rate) -- b1 + the time column x
+// t_k / T_N + the rate's one-hot column -- with the weights and the time
+// feature BF16-rounded as in training.
 __global__ void __launch_bounds__(64) mlp_tables_kernel(
     const double *__restrict__ tenor, const double *__restrict__ vol, int N, int s, int off,
     double alpha, double beta, double delta_nig, const float *__restrict__ wts,
-    float *__restrict__ K2, float *__restrict__ B1, float *__restrict__ W1T) {
+    float *__restrict__ K2, float *__restrict__ B1) {
     const int k = blockIdx.x;
     const int t = threadIdx.x;
     const int m = k / s;
@@ -323,46 +376,37 @@ __global__ void __launch_bounds__(64) mlp_tables_kernel(
         const float wi = static_cast<float>(static_cast<__bf16>(wts[kOffW1 + t * kIn + 1 + kRates + r]));
         B1[((size_t)k * kRates + r) * kHid + t] = bt + wi;
     }
-    if (k == 0)
-        for (int e = t; e < kIn * kHid; e += 64) {
-            const int c = e / kHid, h = e % kHid;
-            W1T[e] = static_cast<float>(static_cast<__bf16>(wts[kOffW1 + h * kIn + c]));
-        }
 }
 
 }  // namespace
 
 hipError_t launch_mlp_tables(const lll_plan &p, const float *wts, float *K2, float *B1,
-                             float *W1T, hipStream_t st) {
+                             hipStream_t st) {
     static_assert(kHid == 64, "one thread per hidden unit");
     hipLaunchKernelGGL(mlp_tables_kernel, dim3(p.K), dim3(64), 0, st, p.d.tenor, p.d.vol, p.N, p.s,
-                       p.off, p.alpha, p.beta, p.delta_nig, wts, K2, B1, W1T);
+                       p.off, p.alpha, p.beta, p.delta_nig, wts, K2, B1);
     return hipGetLastError();
 }
 
 hipError_t launch_mlp_paths(const lll_plan &p, const float *wts, const __bf16 *wbf,
-                            const float *K2, const float *B1, const float *W1T,
-                            const float *box, float sigma, int use_net, int judge_stride,
-                            int64_t n_paths, uint64_t seed, double *path_fix, double *stats,
-                            hipStream_t st) {
+                            const float *K2, const float *B1, const float *box, float sigma,
+                            int use_net, int judge_stride, int64_t n_paths, uint64_t seed,
+                            double *path_fix, double *stats, hipStream_t st) {
     if (p.nmax != kSlots) return hipErrorInvalidValue;
     PathArgs<float> a = detail::make_args<float>(p, seed, n_paths, 0, path_fix);
     MlpArgs g;
-    g.W1T = detail::as_const(W1T);
     g.wf = detail::as_const(wts);
-    g.W2 = wbf + kOffW2;
-    g.W3 = wbf + kOffW3;
+    g.wfv = wts;
+    g.wbf = wbf;
     g.K2 = detail::as_const(K2);
-    g.lo = detail::as_const(box);
-    g.hi = detail::as_const(box + kRates);
-    g.B1 = detail::as_const(B1);
+    // the trust box arrays are per rate; the kernel indexes them by slot
+    g.lo = detail::as_const(box) - p.off;
+    g.hi = detail::as_const(box + kRates) - p.off;
+    g.B1 = B1;
     g.stats = stats;
     g.sigma = sigma;
     g.use_net = use_net;
     g.judge_stride = judge_stride;
-    // the trust box arrays are per rate; the kernel indexes them by slot
-    g.lo = g.lo - p.off;
-    g.hi = g.hi - p.off;
     const dim3 grid(static_cast<unsigned>((n_paths + kBlock - 1) / kBlock));
     hipLaunchKernelGGL(mlp_path_kernel<kFull>, grid, dim3(kBlock), 0, st, a, g);
     return hipGetLastError();
