@@ -189,8 +189,12 @@ __device__ __forceinline__ void layer2(const __bf16 *Wp, int lane, const bf16x8 
         }
 }
 
+// Two wavefronts per SIMD (256 registers each, two 63 KiB blocks per CU): left
+// to itself the compiler takes ~300 registers and one wavefront, which runs
+// the pass 1.6x slower (956 vs 581 ms at 2^20 paths).
 template <int SCHEME>
-__global__ void __launch_bounds__(kBlock) mlp_path_kernel(PathArgs<float> a, MlpArgs g) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
+mlp_path_kernel(PathArgs<float> a, MlpArgs g) {
     // 63 KiB: three padded weight tiles (shared) and one state tile per wavefront
     __shared__ __attribute__((aligned(16))) __bf16 W1p[kHid * kLd];
     __shared__ __attribute__((aligned(16))) __bf16 W2p[kHid * kLd];
