@@ -162,8 +162,8 @@ __device__ __forceinline__ void reverse_step(const PathArgs<float> &a, const Adj
     for (int j = JC; j < NMAX; ++j) {
         const float t = lb[j] * mdt * ell[j] * (1.0f - ell[j]);
         Xb[j] += t;
-        accL0[j * kAdjBlock + lane] += t * static_cast<float>(g.inv_L0[j]);
-        accV[j * kAdjBlock + lane] += vb[j] * mdt;
+        accL0[(j - JC) * kAdjBlock + lane] += t * static_cast<float>(g.inv_L0[j]);
+        accV[(j - JC) * kAdjBlock + lane] += vb[j] * mdt;
     }
 }
 
@@ -179,9 +179,9 @@ __device__ __forceinline__ void sweep(const PathArgs<float> &a, const AdjArgs &g
     const uint32_t p_hi = static_cast<uint32_t>(static_cast<uint64_t>(p) >> 32);
     const int64_t gl = active ? gid : 0;  // lanes past the end read path 0 and contribute 0
 #pragma unroll
-    for (int j = 0; j < NMAX; ++j) {
-        accL0[j * kAdjBlock + lane] = 0.0f;
-        accV[j * kAdjBlock + lane] = 0.0f;
+    for (int j = JC; j < NMAX; ++j) {
+        accL0[(j - JC) * kAdjBlock + lane] = 0.0f;
+        accV[(j - JC) * kAdjBlock + lane] = 0.0f;
     }
     // state at the fixing date T_{c+1}
     float X[NMAX], X1[NMAX], Xb[NMAX];
@@ -212,12 +212,12 @@ __device__ __forceinline__ void sweep(const PathArgs<float> &a, const AdjArgs &g
         const float dD = itm ? static_cast<float>(Lc - K) : 0.0f;
         const float Df = static_cast<float>(D);
         Xb[JC] = dXc;
-        accL0[JC * kAdjBlock + lane] += dXc * static_cast<float>(g.inv_L0[JC]);
+        accL0[lane] += dXc * static_cast<float>(g.inv_L0[JC]);
 #pragma unroll
         for (int j = JC + 1; j < NMAX; ++j) {
             const float t = dD * Df * ellf[j];
             Xb[j] = t;
-            accL0[j * kAdjBlock + lane] += t * static_cast<float>(g.inv_L0[j]);
+            accL0[(j - JC) * kAdjBlock + lane] += t * static_cast<float>(g.inv_L0[j]);
         }
     }
     // skip the sweep when no lane of the wavefront has a nonzero adjoint
@@ -255,8 +255,8 @@ __device__ __forceinline__ void sweep(const PathArgs<float> &a, const AdjArgs &g
     const int64_t wave = gid / kWave;
     double *out = g.gpart + (static_cast<int64_t>(wave) * N + c) * 2 * N;
     for (int j = JC; j < NMAX; ++j) {
-        const double l0 = detail::wave_sum(active ? accL0[j * kAdjBlock + lane] : 0.0f);
-        const double vv = detail::wave_sum(active ? accV[j * kAdjBlock + lane] : 0.0f);
+        const double l0 = detail::wave_sum(active ? accL0[(j - JC) * kAdjBlock + lane] : 0.0f);
+        const double vv = detail::wave_sum(active ? accV[(j - JC) * kAdjBlock + lane] : 0.0f);
         if (lane == 0) {
             out[j - a.off] = l0;
             out[N + j - a.off] = vv;
@@ -273,8 +273,10 @@ __device__ __forceinline__ void sweep(const PathArgs<float> &a, const AdjArgs &g
 // register allocation covers only its own live set.
 template <int NMAX, int JC>
 __global__ void __launch_bounds__(kAdjBlock) sweep_kernel(PathArgs<float> a, AdjArgs g) {
-    __shared__ float accL0[NMAX * kAdjBlock];
-    __shared__ float accV[NMAX * kAdjBlock];
+    // per-lane accumulators of the carried slots JC..NMAX-1 only (LDS bounds
+    // the resident wavefronts of the long sweeps)
+    __shared__ float accL0[(NMAX - JC) * kAdjBlock];
+    __shared__ float accV[(NMAX - JC) * kAdjBlock];
     const int64_t gid = static_cast<int64_t>(blockIdx.x) * kAdjBlock + threadIdx.x;
     const int64_t wave_first = gid - threadIdx.x;
     if (wave_first >= a.n_paths) return;
