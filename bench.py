@@ -60,6 +60,8 @@ def flops_per_path_step(scheme: str, n: int) -> int:
         return 6 * Q * (n - 1) + Q + 16 * n + 40
     if scheme == "frozen":
         return 4 * n + 40
+    if scheme == "first_order":       # n (n - 1) / 2 FMAs of the closed-form sums
+        return n * (n - 1) + 8 * n + 40
     raise ValueError(scheme)
 
 
@@ -152,7 +154,7 @@ def bench_mlp(lll, stream, n: int = 1 << 20, train_steps: int = 3000) -> dict:
         legs = [("full", lambda: plan.execute(lll.FULL, n, seed=1, stream=stream)),
                 ("picard", lambda: plan.execute(lll.PICARD, n, seed=1, stream=stream)),
                 ("frozen", lambda: plan.execute(lll.FROZEN, n, seed=1, stream=stream)),
-                ("first_order", lambda: plan.execute_mlp(None, False, n, seed=1, stream=stream)),
+                ("first_order", lambda: plan.execute(lll.FIRST_ORDER, n, seed=1, stream=stream)),
                 ("mlp", lambda: plan.execute_mlp(net, True, n, seed=1, stream=stream))]
         prices = {}
         for name, run in legs:
@@ -181,9 +183,31 @@ def bench_mlp(lll, stream, n: int = 1 << 20, train_steps: int = 3000) -> dict:
     t = out["mlp"]["kernel_ms"] / 1e3
     out["mlp"].update({"mfma_tflops": mf * n / t / 1e12, "frac_bf16_peak": mf * n / t / PEAK_BF16,
                        "valu_tflops": va * n / t / 1e12, "frac_fp32_peak": va * n / t / PEAK_FP32})
-    for name in ("full", "picard"):
+    for name in ("full", "picard", "first_order"):
         fl = flops_per_path(ts, name) * n
         out[name]["frac_fp32_peak"] = fl / (out[name]["kernel_ms"] / 1e3) / PEAK_FP32
+    return out
+
+
+def bench_reference_schemes(lll, plan, ts, n, stream) -> dict:
+    """The frozen drift and the first-order expansion on the benchmark workload:
+    path-kernel time (HIP events) and max relative caplet error against FULL on
+    the same streams (not part of `value`)."""
+    plan.execute(lll.FULL, n, seed=1, stream=stream)
+    full = plan.results(stream)["price"]
+    live = full > 0.0
+    out = {}
+    for name in ("frozen", "first_order"):
+        plan.execute(lll.SCHEMES[name], n, seed=1, stream=stream)   # warmup
+        ms = []
+        for _ in range(3):
+            plan.execute(lll.SCHEMES[name], n, seed=1, stream=stream)
+            ms.append(plan.timing()["paths"])
+        t = float(np.median(ms)) / 1e3
+        price = plan.results(stream)["price"]
+        out[name] = {"path_kernel_ms": t * 1e3, "path_steps_per_s": n * ts.n_steps / t,
+                     "frac_fp32_peak": flops_per_path(ts, name) * n / t / PEAK_FP32,
+                     "max_rel_err_vs_full": float(np.max(np.abs(price[live] / full[live] - 1)))}
     return out
 
 
@@ -317,6 +341,7 @@ def main(argv=None) -> int:
         "schemes": per_scheme,
         "wall_s": wall,
     }
+    out["reference_schemes"] = bench_reference_schemes(lll, plan, ts, n, stream)
     if args.batched:
         out["batched"] = bench_batched(lll, stream, schemes)
     if args.adjoint:

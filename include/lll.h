@@ -5,12 +5,16 @@
  * One call prices caplets (paper Section 3.3, eq. (caplet)) by simulating
  * log-LIBOR rates under the terminal measure P_{T_*} (Section 2, eqs.
  * (LIBOR-dyn-PT), (LIBOR-drift-PT), (log-LIB-SIE)) with an Euler scheme and
- * one of three drift treatments (Section 3):
+ * one of four drift treatments (Section 3):
  *
  *   LLL_FULL    the drift of eq. (LIBOR-drift-PT) at the current rates;
  *   LLL_PICARD  the drift of eq. (bdrift), evaluated at the second Picard
  *               iterate Z^(1) of eq. (Picard-2);
  *   LLL_FROZEN  Z^(1) itself (the drift frozen at the initial rates);
+ *   LLL_FIRST_ORDER  the drift at the current rates with the product of eq.
+ *               (LIBOR-drift-PT) expanded to first order in ell (Section 3.2,
+ *               eq. (drifta)), in closed form through the cumulant (no
+ *               quadrature); error O(|L|^2);
  *
  * driven by a normal inverse Gaussian Lévy process (Section 4) or, as a
  * special case, by a Brownian motion.  The jump integral of the drift is the
@@ -62,7 +66,7 @@ typedef enum {
     LLL_ENUMERIC = -6      /* non-finite payoffs were produced */
 } lll_status;
 
-typedef enum { LLL_FULL = 0, LLL_PICARD = 1, LLL_FROZEN = 2 } lll_scheme;
+typedef enum { LLL_FULL = 0, LLL_PICARD = 1, LLL_FROZEN = 2, LLL_FIRST_ORDER = 3 } lll_scheme;
 typedef enum { LLL_DRIVER_NIG = 0, LLL_DRIVER_BROWNIAN = 1 } lll_driver;
 typedef enum { LLL_FP32 = 0, LLL_FP64 = 1 } lll_precision;
 
@@ -102,8 +106,11 @@ const char *lll_last_error(void);
 int lll_plan_create(const lll_term_structure *ts, int precision, int64_t max_paths,
                     lll_plan **plan_out);
 
-/* Enqueue one pricing pass on `stream`: FP64 precompute of the quadrature rule
- * and of the cumulant, quadrature and frozen-drift tables; the path kernel over
+/* Enqueue one pricing pass on `stream` with `scheme` (lll_scheme; LLL_EINVAL
+ * otherwise): FP64 precompute of the quadrature rule and of the cumulant,
+ * quadrature and frozen-drift tables (LLL_FIRST_ORDER: also the per-step
+ * coefficients kappa(lambda_i + lambda_l) - kappa(lambda_i) - kappa(lambda_l),
+ * allocated on its first use, LLL_ENOMEM if that fails); the path kernel over
  * paths path_offset .. path_offset + n_paths - 1; the deterministic FP64
  * reduction of the payoff sums.  Asynchronous: results are read with
  * lll_plan_results.  If path_fix_dev is not NULL it receives, for every path
@@ -267,7 +274,8 @@ int lll_batch_create(const lll_term_structure *ts, int n_ts, int64_t max_paths_e
                      lll_batch **batch_out);
 
 /* Price every structure with n_paths_each paths in one persistent kernel
- * launch on `stream`: work items of 256 paths, longest tenors first, pulled
+ * launch on `stream` (schemes LLL_FULL, LLL_PICARD, LLL_FROZEN; LLL_EINVAL
+ * otherwise): work items of 256 paths, longest tenors first, pulled
  * from a device counter by a grid sized to the GPU's resident capacity; then
  * each structure's fixed-order reduction.  Blocks the host briefly while the
  * work list is copied to the device; the pricing itself is asynchronous. */

@@ -27,7 +27,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lll_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liblll_oracle.so")
 
-FULL, PICARD, FROZEN = 0, 1, 2
+FULL, PICARD, FROZEN, FIRST_ORDER = 0, 1, 2, 3
 NIG, BROWNIAN = 0, 1
 
 
@@ -89,6 +89,7 @@ def _load():
         lib.oracle_increment.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, dp, dp,
                                          ctypes.POINTER(ctypes.c_uint32)]
         lib.oracle_drift.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, dp, dp]
+        lib.oracle_drift_first_order.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, dp, dp]
         lib.oracle_paths.argtypes = [ctypes.c_void_p, ctypes.c_int,
                                      ctypes.POINTER(ctypes.c_int64), ctypes.c_int64, dp, dp]
         lib.oracle_paths.restype = ctypes.c_int
@@ -203,12 +204,14 @@ class Oracle:
         self._lib.oracle_increments(self._ctx, int(k), int(p0), int(n), _dp(V), _dp(dH))
         return V, dH
 
-    def drift(self, k: int, L: np.ndarray) -> np.ndarray:
-        """Drift b(t_k, T_i) of the live rates at step k for given rates L (len N)."""
+    def drift(self, k: int, L: np.ndarray, first_order: bool = False) -> np.ndarray:
+        """Drift b(t_k, T_i) of the live rates at step k for given rates L (len N);
+        with first_order, its first-order expansion (eq. (drifta))."""
         L = np.ascontiguousarray(np.asarray(L, dtype=np.float64))
         b = np.zeros(self.N)
         first = k // self.s
-        self._lib.oracle_drift(self._ctx, int(k), int(first), _dp(L), _dp(b))
+        fn = self._lib.oracle_drift_first_order if first_order else self._lib.oracle_drift
+        fn(self._ctx, int(k), int(first), _dp(L), _dp(b))
         b[:first] = np.nan
         return b
 

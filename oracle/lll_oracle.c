@@ -24,7 +24,9 @@
  *   - three schemes (Section 3): FULL uses the drift at the current rates;
  *     PICARD uses the drift evaluated at the second Picard iterate Z^(1)
  *     (eq. (bdrift)), itself driven by the deterministic drift at Z(0)
- *     (eq. (Picard-2)); FROZEN is Z^(1) itself;
+ *     (eq. (Picard-2)); FROZEN is Z^(1) itself; and FIRST_ORDER, the drift
+ *     at the current rates with the product replaced by its first-order
+ *     expansion (Section 3.2, eq. (drifta)), in closed form through kappa;
  *   - the caplet payoff under the terminal measure (Section 3.3, eq. (caplet)):
  *       delta_i B(0,T_*) E[ prod_{l>i} (1 + delta_l L(T_i,T_l)) (L(T_i,T_i) - K)^+ ];
  *     this file returns path sums; the Python wrapper forms prices.
@@ -49,6 +51,7 @@
 #define ORACLE_FULL 0
 #define ORACLE_PICARD 1
 #define ORACLE_FROZEN 2
+#define ORACLE_FIRST_ORDER 3
 
 #define ORACLE_NIG 0
 #define ORACLE_BROWNIAN 1
@@ -211,6 +214,29 @@ void oracle_drift(const oracle_ctx *ctx, int k, int first, const double *L, doub
     }
 }
 
+/* First-order drift expansion (Section 3.2, eq. (drifta)): the product over
+ * l > i truncated after its terms linear in ell, each integral in closed form,
+ *   b_i = -kappa(lambda_i)
+ *         - sum_{l>i} ell_l (kappa(lambda_i + lambda_l) - kappa(lambda_i) - kappa(lambda_l)).
+ * For the Brownian driver the coupling is linear in ell, so this equals the
+ * exact drift. */
+void oracle_drift_first_order(const oracle_ctx *ctx, int k, int first, const double *L, double *b)
+{
+    const oracle_model *m = &ctx->m;
+    const int N = m->n_rates;
+    const double *lam = m->vol + (size_t)k * N;
+    double ell[64];
+    for (int l = first; l < N; ++l)
+        ell[l] = m->delta[l] * L[l] / (1.0 + m->delta[l] * L[l]);
+    for (int i = first; i < N; ++i) {
+        const double ki = cumulant(ctx, lam[i]);
+        double coupling = 0.0;
+        for (int l = i + 1; l < N; ++l)
+            coupling += ell[l] * (cumulant(ctx, lam[i] + lam[l]) - ki - cumulant(ctx, lam[l]));
+        b[i] = -ki - coupling;
+    }
+}
+
 /* ---------------- set-up ---------------- */
 
 oracle_ctx *oracle_create(const oracle_model *model)
@@ -287,6 +313,9 @@ static void simulate_path(const oracle_ctx *ctx, int scheme, int64_t p, double *
             if (scheme == ORACLE_FULL) {
                 for (int i = mth; i < N; ++i) L[i] = m->L0[i] * exp(X[i]);
                 oracle_drift(ctx, k, mth, L, b);
+            } else if (scheme == ORACLE_FIRST_ORDER) {
+                for (int i = mth; i < N; ++i) L[i] = m->L0[i] * exp(X[i]);
+                oracle_drift_first_order(ctx, k, mth, L, b);
             } else if (scheme == ORACLE_PICARD) {
                 for (int i = mth; i < N; ++i) L[i] = m->L0[i] * exp(X1[i]);
                 oracle_drift(ctx, k, mth, L, b);

@@ -5,7 +5,7 @@ The computation lives in the HIP library ``liblll.so`` behind the C ABI of
 package does not load the library; the first call does, and raises if the
 library is missing.
 """
-from ._lib import (FP32, FP64, FROZEN, FULL, PICARD, Batch, LLLError, Mlp, Plan,  # noqa: F401
+from ._lib import (FIRST_ORDER, FP32, FP64, FROZEN, FULL, PICARD, Batch, LLLError, Mlp, Plan,  # noqa: F401
                    caplet_greeks, load, philox, price_caplets, version)
 
-SCHEMES = {"full": FULL, "picard": PICARD, "frozen": FROZEN}
+SCHEMES = {"full": FULL, "picard": PICARD, "frozen": FROZEN, "first_order": FIRST_ORDER}

@@ -110,7 +110,7 @@ hipError_t dalloc(T **p, size_t n) {
 
 void free_tables(lll::DeviceTables &d) {
     void *ptrs[] = {d.tenor, d.delta, d.L0, d.vol, d.strikes, d.x, d.w, d.kappa, d.E, d.b0,
-                    d.steps, d.lam_pm, d.ew, d.lam, d.drift0, d.frozen, d.dt, d.cinv, d.L0s,
+                    d.steps, d.lam_pm, d.ew, d.lam, d.drift0, d.frozen, d.dt, d.cinv, d.k2, d.L0s,
                     d.deltas, d.partials, d.chunks, d.sums, d.results};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -263,17 +263,27 @@ int lll_plan_destroy(lll_plan *plan) {
 int lll_plan_execute(lll_plan *plan, int scheme, int64_t n_paths, int64_t path_offset,
                      uint64_t seed, double *path_fix_dev, void *stream) {
     if (!plan) return fail(LLL_EINVAL, "plan is NULL");
-    if (scheme != LLL_FULL && scheme != LLL_PICARD && scheme != LLL_FROZEN)
+    if (scheme != LLL_FULL && scheme != LLL_PICARD && scheme != LLL_FROZEN &&
+        scheme != LLL_FIRST_ORDER)
         return fail(LLL_EINVAL, "unknown scheme %d", scheme);
     if (n_paths < 1 || n_paths > plan->max_paths)
         return fail(LLL_EINVAL, "n_paths=%lld outside 1..%lld", (long long)n_paths,
                     (long long)plan->max_paths);
     if (path_offset < 0 || path_offset > ((int64_t)1 << 62))
         return fail(LLL_EINVAL, "path_offset=%lld out of range", (long long)path_offset);
+    if (scheme == LLL_FIRST_ORDER && !plan->d.k2) {
+        const size_t esz = plan->precision == LLL_FP64 ? sizeof(double) : sizeof(float);
+        hipError_t ea = hipMalloc(&plan->d.k2, (size_t)plan->K * plan->nmax * plan->nmax * esz);
+        if (ea != hipSuccess) {
+            plan->d.k2 = nullptr;
+            return fail(LLL_ENOMEM, "first-order table: %s", hipGetErrorString(ea));
+        }
+    }
     hipStream_t st = as_stream(stream);
     const bool t = plan->timing;
     hipError_t e = t ? hipEventRecord(plan->ev[0], st) : hipSuccess;
     if (e == hipSuccess) e = lll::launch_precompute(*plan, st);
+    if (e == hipSuccess && scheme == LLL_FIRST_ORDER) e = lll::launch_first_order_tables(*plan, st);
     if (e != hipSuccess) return hip_fail(e, "precompute launch");
     if (t) e = hipEventRecord(plan->ev[1], st);
     if (e == hipSuccess) e = lll::launch_paths(*plan, scheme, n_paths, path_offset, seed,

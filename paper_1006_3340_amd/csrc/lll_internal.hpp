@@ -36,6 +36,7 @@ struct DeviceTables {
     void *frozen = nullptr;    // [K][nmax]  b0 dt
     void *dt = nullptr;        // [K]
     void *cinv = nullptr;      // [nmax]  1 / (delta L0)
+    void *k2 = nullptr;        // [K][nmax][nmax] first-order coefficients (allocated on first use)
     double *L0s = nullptr, *deltas = nullptr;   // [nmax] FP64 slot layout
     // reduction
     double *partials = nullptr;  // [max_waves][N][NSTAT]
@@ -97,6 +98,9 @@ constexpr int kStatBase = 3;  // NSTAT = 3 S + 2
 // abi.hip: thread-local error text of the C ABI
 int fail(int code, const char *fmt, ...);
 int hip_fail(hipError_t e, const char *what);
+
+// precompute.hip: first-order coefficients K2 (scheme LLL_FIRST_ORDER)
+hipError_t launch_first_order_tables(const lll_plan &p, hipStream_t st);
 
 // adjoint.hip
 hipError_t greeks_alloc(lll_plan &p);

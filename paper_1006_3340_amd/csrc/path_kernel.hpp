@@ -53,6 +53,7 @@ struct PathArgs {
     cptr<Real> frozen;     // [K][nmax]
     cptr<Real> dt;         // [K]
     cptr<Real> cinv;       // [nmax]
+    cptr<Real> k2;         // [K][nmax][nmax] first-order coefficients, or null
     cptr<double> L0s;      // [nmax]
     cptr<double> deltas;   // [nmax]
     cptr<double> strikes;  // [N][S]
@@ -113,6 +114,34 @@ __device__ __forceinline__ void brownian_coupling(cptr<Real> lamk, Real cR,
     }
 }
 
+// First-order expansion of the coupling (Section 3.2, eq. (drifta)):
+// C_j = sum_{l>j} ell_l K2_{k,j,l}, K2 = kappa(lambda_j + lambda_l) - kappa(lambda_j)
+// - kappa(lambda_l) from the step's table (wave-uniform scalar operands).
+template <typename Real, int NMAX, int J0>
+__device__ __forceinline__ void first_order_coupling(cptr<Real> k2k, const Real (&ell)[NMAX],
+                                                     Real (&C)[NMAX]) {
+#pragma unroll
+    for (int j = J0; j < NMAX; ++j) {
+        Real c = Real(0);
+#pragma unroll
+        for (int l = j + 1; l < NMAX; ++l) c = fma(ell[l], k2k[j * NMAX + l], c);
+        C[j] = c;
+    }
+}
+
+// Coupling sums of the scheme: the first-order expansion, the Brownian
+// closed form or the 64-node quadrature.
+template <typename Real, int NMAX, int SCHEME, int J0>
+__device__ __forceinline__ void coupling(const PathArgs<Real> &a, int k, const Real (&ell)[NMAX],
+                                         Real (&C)[NMAX]) {
+    if constexpr (SCHEME == kFirst)
+        first_order_coupling<Real, NMAX, J0>(a.k2 + (size_t)k * NMAX * NMAX, ell, C);
+    else if (a.brownian)
+        brownian_coupling<Real, NMAX, J0>(a.lam + (size_t)k * NMAX, static_cast<Real>(a.c), ell, C);
+    else
+        quad_coupling<Real, NMAX, J0>(a.ew + (size_t)k * kQ * NMAX * 2, ell, C);
+}
+
 // One Euler step for the live slots J0 .. NMAX-1 (drift and state update).
 template <typename Real, int NMAX, int SCHEME, int J0>
 __device__ __forceinline__ void step(const PathArgs<Real> &a, int k, Real dH, Real (&X)[NMAX],
@@ -128,10 +157,7 @@ __device__ __forceinline__ void step(const PathArgs<Real> &a, int k, Real dH, Re
         for (int j = J0; j < NMAX; ++j)
             ell[j] = ell_of(SCHEME == kPicard ? X1[j] : X[j], a.cinv[j]);
         Real C[NMAX];
-        if (a.brownian)
-            brownian_coupling<Real, NMAX, J0>(lamk, static_cast<Real>(a.c), ell, C);
-        else
-            quad_coupling<Real, NMAX, J0>(a.ew + (size_t)k * kQ * NMAX * 2, ell, C);
+        coupling<Real, NMAX, SCHEME, J0>(a, k, ell, C);
         const Real dt = a.dt[k];
         const cptr<Real> d0k = a.drift0 + (size_t)k * NMAX;
 #pragma unroll
@@ -200,10 +226,7 @@ __device__ __forceinline__ void step_lds(const PathArgs<Real> &a, int k, Real dH
         ell[j] = ell_of(SCHEME == kPicard ? X1[j] : xs[j * kBlock], a.cinv[j]);
     __asm__ volatile("" ::: "memory");
     Real C[NMAX];
-    if (a.brownian)
-        brownian_coupling<Real, NMAX, J0>(lamk, static_cast<Real>(a.c), ell, C);
-    else
-        quad_coupling<Real, NMAX, J0>(a.ew + (size_t)k * kQ * NMAX * 2, ell, C);
+    coupling<Real, NMAX, SCHEME, J0>(a, k, ell, C);
     const Real dt = a.dt[k];
     const cptr<Real> d0k = a.drift0 + (size_t)k * NMAX;
 #pragma unroll
@@ -391,6 +414,7 @@ inline PathArgs<Real> make_args(const lll_plan &p, uint64_t seed, int64_t n_path
     a.frozen = as_const(static_cast<const Real *>(d.frozen));
     a.dt = as_const(static_cast<const Real *>(d.dt));
     a.cinv = as_const(static_cast<const Real *>(d.cinv));
+    a.k2 = as_const(static_cast<const Real *>(d.k2));
     a.L0s = as_const<double>(d.L0s);
     a.deltas = as_const<double>(d.deltas);
     a.strikes = as_const<double>(d.strikes);
@@ -421,6 +445,9 @@ hipError_t launch_paths_n(const PathArgs<Real> &a, int scheme, int64_t n_paths, 
             break;
         case kPicard:
             hipLaunchKernelGGL((path_kernel<Real, NMAX, kPicard>), grid, dim3(kBlock), 0, st, a);
+            break;
+        case kFirst:
+            hipLaunchKernelGGL((path_kernel<Real, NMAX, kFirst>), grid, dim3(kBlock), 0, st, a);
             break;
         default:
             hipLaunchKernelGGL((path_kernel<Real, NMAX, kFrozen>), grid, dim3(kBlock), 0, st, a);

@@ -220,7 +220,48 @@ hipError_t launch_precompute_t(const lll_plan &p, hipStream_t st) {
     return hipGetLastError();
 }
 
+// First-order expansion of the coupling (paper Section 3.2, eq. (drifta)):
+// K2[k][j][l] = kappa(lambda_j + lambda_l) - kappa(lambda_j) - kappa(lambda_l)
+// for live slots j < l at step k, 0 elsewhere; FP64, stored in the plan
+// precision.  One block per step.
+template <typename Real>
+__global__ void __launch_bounds__(64) setup_first_order_kernel(
+    const double *__restrict__ vol, int N, int s, int off, int nmax, int driver, double alpha,
+    double beta, double delta_nig, double c, Real *__restrict__ k2) {
+    const int k = blockIdx.x;
+    const int m = k / s;
+    const double *lam = vol + (size_t)k * N;
+    const bool nig = driver == LLL_DRIVER_NIG;
+    for (int e = threadIdx.x; e < nmax * nmax; e += 64) {
+        const int j = e / nmax, l = e % nmax;
+        const int rj = j - off, rl = l - off;
+        double v = 0.0;
+        if (rj >= m && rl > rj) {
+            const double a = lam[rj], b = lam[rl];
+            v = nig ? nig_cumulant(a + b, alpha, beta, delta_nig) -
+                          nig_cumulant(a, alpha, beta, delta_nig) -
+                          nig_cumulant(b, alpha, beta, delta_nig)
+                    : c * a * b;  // c (a + b)^2 / 2 - c a^2 / 2 - c b^2 / 2
+        }
+        k2[(size_t)k * nmax * nmax + e] = static_cast<Real>(v);
+    }
+}
+
+template <typename Real>
+hipError_t launch_first_order_t(const lll_plan &p, hipStream_t st) {
+    hipLaunchKernelGGL(setup_first_order_kernel<Real>, dim3(p.K), dim3(64), 0, st, p.d.vol, p.N,
+                       p.s, p.off, p.nmax, p.driver, p.alpha, p.beta, p.delta_nig, p.c,
+                       static_cast<Real *>(p.d.k2));
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_first_order_tables(const lll_plan &p, hipStream_t st) {
+    if (!p.d.k2) return hipErrorInvalidValue;
+    return p.precision == LLL_FP64 ? launch_first_order_t<double>(p, st)
+                                   : launch_first_order_t<float>(p, st);
+}
 
 hipError_t launch_precompute(const lll_plan &p, hipStream_t st) {
     return p.precision == LLL_FP64 ? launch_precompute_t<double>(p, st)

@@ -198,6 +198,21 @@ def test_empty_trust_box_is_full_euler(gpu_lib, trained):
         net.set_box(np.full(40, np.nan), np.ones(40))
 
 
+def test_first_order_scheme_matches_surrogate_kernel_without_network(gpu_lib, trained):
+    """The path kernel's first-order scheme and the surrogate kernel without its
+    network evaluate the same drift (eq. (drifta)) on the same streams, in FP32
+    with different summation orders."""
+    ts, plan, _, _, _ = trained
+    n = 1 << 14
+    plan.execute(3, n, seed=2)
+    a = plan.results()
+    plan.execute_mlp(None, False, n, seed=2)
+    b = plan.results()
+    live = a["price"] > 0
+    assert np.all(np.abs(b["price"][live] / a["price"][live] - 1.0) < 1e-6)
+    assert np.array_equal(a["n_itm"], b["n_itm"])
+
+
 def test_surrogate_gain_over_first_order(gpu_lib, trained):
     """Prices on common random numbers at the benchmark size (2^20 paths): the
     surrogate against the FULL quadrature drift, next to the first-order

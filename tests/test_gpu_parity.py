@@ -25,8 +25,8 @@ import workloads
 
 pytestmark = pytest.mark.gpu
 
-FULL, PICARD, FROZEN = 0, 1, 2
-SCHEMES = (FULL, PICARD, FROZEN)
+FULL, PICARD, FROZEN, FIRST_ORDER = 0, 1, 2, 3
+SCHEMES = (FULL, PICARD, FROZEN, FIRST_ORDER)
 
 
 def _oracle(oracle_mod, ts, seed=1):

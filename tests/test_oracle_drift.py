@@ -186,3 +186,47 @@ def test_drift_expansion_orders(oracle_mod):
     # the printed sign leaves an O(ell) error, far larger than A''
     assert 1.6 < e[0, 2] / e[1, 2] < 2.4
     assert e[0, 2] > 1e3 * e[0, 1]
+
+
+def test_first_order_drift_of_the_oracle(oracle_mod):
+    """The oracle's first-order drift (eq. (drifta)) is the A' of the test above
+    (an independent transcription), its error against the product-form drift
+    shrinks 4x when the forwards halve, and at N = 40 it agrees with the
+    surrogate reference's first-order coupling."""
+    from oracle import mlp as M
+    ts = workloads.plain_fp64()
+    o = oracle_mod.Oracle(ts)
+    kap = lambda u: float(kappa_nig(u, ts.alpha, ts.beta, ts.delta_nig))
+    errs = []
+    for eps in (1.0, 0.5, 0.25):
+        L = ts.L0 * eps
+        b1 = o.drift(0, L, first_order=True)
+        ell = ts.delta * L / (1.0 + ts.delta * L)
+        a1, _, _ = _expansions(ts.vol[0], ell, 0, kap)
+        assert abs(-b1[0] - a1) <= 1e-14 * abs(a1)
+        errs.append(abs(b1[0] - o.drift(0, L)[0]))
+    assert 3.2 < errs[0] / errs[1] < 4.8 and 3.2 < errs[1] / errs[2] < 4.8
+    t40 = workloads.learned_drift()
+    o40 = oracle_mod.Oracle(t40)
+    k = 137
+    m = k // t40.steps_per_period
+    L = t40.L0 * np.exp(np.linspace(-0.2, 0.3, 40))
+    b1 = o40.drift(k, L, first_order=True)
+    ell = t40.delta * L / (1.0 + t40.delta * L)
+    ell[:m] = 0.0
+    C1 = M.first_order_coupling(ell[None, :], np.asarray(t40.vol[k]), t40)[0]
+    assert np.allclose(-b1[m:] - o40.kappa[k, m:], C1[m:], rtol=1e-12, atol=1e-18)
+
+
+def test_first_order_scheme_is_exact_for_brownian_driver(oracle_mod):
+    """With a Brownian driver the coupling c lambda_i sum ell_l lambda_l is linear
+    in ell, so the first-order scheme reproduces the full scheme."""
+    ts = workloads.brownian()
+    o = oracle_mod.Oracle(ts)
+    L = ts.L0 * 1.3
+    for k in (0, 25, 100):
+        assert np.allclose(o.drift(k, L, first_order=True), o.drift(k, L), rtol=1e-14,
+                           atol=0, equal_nan=True)
+    a = o.price(3, 500)
+    b = o.price(0, 500)
+    assert np.allclose(a["price"], b["price"], rtol=1e-12, atol=0)
