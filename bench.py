@@ -62,6 +62,8 @@ def flops_per_path_step(scheme: str, n: int) -> int:
         return 4 * n + 40
     if scheme == "first_order":       # n (n - 1) / 2 FMAs of the closed-form sums
         return n * (n - 1) + 8 * n + 40
+    if scheme == "second_order":      # 7 flops per (rate, node): C += W E s, t, s, u
+        return 7 * Q * (n - 1) + Q + 8 * n + 40
     raise ValueError(scheme)
 
 
@@ -155,6 +157,7 @@ def bench_mlp(lll, stream, n: int = 1 << 20, train_steps: int = 3000) -> dict:
                 ("picard", lambda: plan.execute(lll.PICARD, n, seed=1, stream=stream)),
                 ("frozen", lambda: plan.execute(lll.FROZEN, n, seed=1, stream=stream)),
                 ("first_order", lambda: plan.execute(lll.FIRST_ORDER, n, seed=1, stream=stream)),
+                ("second_order", lambda: plan.execute(lll.SECOND_ORDER, n, seed=1, stream=stream)),
                 ("mlp", lambda: plan.execute_mlp(net, True, n, seed=1, stream=stream))]
         prices = {}
         for name, run in legs:
@@ -183,21 +186,21 @@ def bench_mlp(lll, stream, n: int = 1 << 20, train_steps: int = 3000) -> dict:
     t = out["mlp"]["kernel_ms"] / 1e3
     out["mlp"].update({"mfma_tflops": mf * n / t / 1e12, "frac_bf16_peak": mf * n / t / PEAK_BF16,
                        "valu_tflops": va * n / t / 1e12, "frac_fp32_peak": va * n / t / PEAK_FP32})
-    for name in ("full", "picard", "first_order"):
+    for name in ("full", "picard", "first_order", "second_order"):
         fl = flops_per_path(ts, name) * n
         out[name]["frac_fp32_peak"] = fl / (out[name]["kernel_ms"] / 1e3) / PEAK_FP32
     return out
 
 
 def bench_reference_schemes(lll, plan, ts, n, stream) -> dict:
-    """The frozen drift and the first-order expansion on the benchmark workload:
+    """The frozen drift and the first- and second-order expansions on the benchmark workload:
     path-kernel time (HIP events) and max relative caplet error against FULL on
     the same streams (not part of `value`)."""
     plan.execute(lll.FULL, n, seed=1, stream=stream)
     full = plan.results(stream)["price"]
     live = full > 0.0
     out = {}
-    for name in ("frozen", "first_order"):
+    for name in ("frozen", "first_order", "second_order"):
         plan.execute(lll.SCHEMES[name], n, seed=1, stream=stream)   # warmup
         ms = []
         for _ in range(3):

@@ -5,7 +5,7 @@
  * One call prices caplets (paper Section 3.3, eq. (caplet)) by simulating
  * log-LIBOR rates under the terminal measure P_{T_*} (Section 2, eqs.
  * (LIBOR-dyn-PT), (LIBOR-drift-PT), (log-LIB-SIE)) with an Euler scheme and
- * one of four drift treatments (Section 3):
+ * one of five drift treatments (Section 3):
  *
  *   LLL_FULL    the drift of eq. (LIBOR-drift-PT) at the current rates;
  *   LLL_PICARD  the drift of eq. (bdrift), evaluated at the second Picard
@@ -15,6 +15,10 @@
  *               (LIBOR-drift-PT) expanded to first order in ell (Section 3.2,
  *               eq. (drifta)), in closed form through the cumulant (no
  *               quadrature); error O(|L|^2);
+ *   LLL_SECOND_ORDER the same expansion to second order (eq. (drifta2), its
+ *               first-order bracket with the signs of eq. (drifta)); the
+ *               truncated product is integrated with the 64-node rule;
+ *               error O(|L|^3);
  *
  * driven by a normal inverse Gaussian Lévy process (Section 4) or, as a
  * special case, by a Brownian motion.  The jump integral of the drift is the
@@ -66,7 +70,13 @@ typedef enum {
     LLL_ENUMERIC = -6      /* non-finite payoffs were produced */
 } lll_status;
 
-typedef enum { LLL_FULL = 0, LLL_PICARD = 1, LLL_FROZEN = 2, LLL_FIRST_ORDER = 3 } lll_scheme;
+typedef enum {
+    LLL_FULL = 0,
+    LLL_PICARD = 1,
+    LLL_FROZEN = 2,
+    LLL_FIRST_ORDER = 3,
+    LLL_SECOND_ORDER = 4
+} lll_scheme;
 typedef enum { LLL_DRIVER_NIG = 0, LLL_DRIVER_BROWNIAN = 1 } lll_driver;
 typedef enum { LLL_FP32 = 0, LLL_FP64 = 1 } lll_precision;
 

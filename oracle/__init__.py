@@ -27,7 +27,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lll_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liblll_oracle.so")
 
-FULL, PICARD, FROZEN, FIRST_ORDER = 0, 1, 2, 3
+FULL, PICARD, FROZEN, FIRST_ORDER, SECOND_ORDER = 0, 1, 2, 3, 4
 NIG, BROWNIAN = 0, 1
 
 
@@ -90,6 +90,7 @@ def _load():
                                          ctypes.POINTER(ctypes.c_uint32)]
         lib.oracle_drift.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, dp, dp]
         lib.oracle_drift_first_order.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, dp, dp]
+        lib.oracle_drift_second_order.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, dp, dp]
         lib.oracle_paths.argtypes = [ctypes.c_void_p, ctypes.c_int,
                                      ctypes.POINTER(ctypes.c_int64), ctypes.c_int64, dp, dp]
         lib.oracle_paths.restype = ctypes.c_int
@@ -204,13 +205,14 @@ class Oracle:
         self._lib.oracle_increments(self._ctx, int(k), int(p0), int(n), _dp(V), _dp(dH))
         return V, dH
 
-    def drift(self, k: int, L: np.ndarray, first_order: bool = False) -> np.ndarray:
+    def drift(self, k: int, L: np.ndarray, order: int = 0) -> np.ndarray:
         """Drift b(t_k, T_i) of the live rates at step k for given rates L (len N);
-        with first_order, its first-order expansion (eq. (drifta))."""
+        order 1 / 2: its expansion of eq. (drifta) / (drifta2) instead."""
         L = np.ascontiguousarray(np.asarray(L, dtype=np.float64))
         b = np.zeros(self.N)
         first = k // self.s
-        fn = self._lib.oracle_drift_first_order if first_order else self._lib.oracle_drift
+        fn = {0: self._lib.oracle_drift, 1: self._lib.oracle_drift_first_order,
+              2: self._lib.oracle_drift_second_order}[order]
         fn(self._ctx, int(k), int(first), _dp(L), _dp(b))
         b[:first] = np.nan
         return b

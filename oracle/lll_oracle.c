@@ -24,9 +24,11 @@
  *   - three schemes (Section 3): FULL uses the drift at the current rates;
  *     PICARD uses the drift evaluated at the second Picard iterate Z^(1)
  *     (eq. (bdrift)), itself driven by the deterministic drift at Z(0)
- *     (eq. (Picard-2)); FROZEN is Z^(1) itself; and FIRST_ORDER, the drift
- *     at the current rates with the product replaced by its first-order
- *     expansion (Section 3.2, eq. (drifta)), in closed form through kappa;
+ *     (eq. (Picard-2)); FROZEN is Z^(1) itself; and FIRST_ORDER /
+ *     SECOND_ORDER, the drift at the current rates with the product replaced
+ *     by its expansion to first / second order in ell (Section 3.2, eqs.
+ *     (drifta), (drifta2) with the sign of the first-order bracket as in
+ *     (drifta)), in closed form through kappa;
  *   - the caplet payoff under the terminal measure (Section 3.3, eq. (caplet)):
  *       delta_i B(0,T_*) E[ prod_{l>i} (1 + delta_l L(T_i,T_l)) (L(T_i,T_i) - K)^+ ];
  *     this file returns path sums; the Python wrapper forms prices.
@@ -52,6 +54,7 @@
 #define ORACLE_PICARD 1
 #define ORACLE_FROZEN 2
 #define ORACLE_FIRST_ORDER 3
+#define ORACLE_SECOND_ORDER 4
 
 #define ORACLE_NIG 0
 #define ORACLE_BROWNIAN 1
@@ -237,6 +240,35 @@ void oracle_drift_first_order(const oracle_ctx *ctx, int k, int first, const dou
     }
 }
 
+/* Second-order drift expansion (Section 3.2, eq. (drifta2), its first-order
+ * bracket read with the signs of eq. (drifta)): the first-order drift plus
+ *   - sum_{i<k<l} ell_k ell_l ( kappa(lambda_i + lambda_k + lambda_l)
+ *       - kappa(lambda_i + lambda_k) - kappa(lambda_i + lambda_l) - kappa(lambda_k + lambda_l)
+ *       + kappa(lambda_i) + kappa(lambda_k) + kappa(lambda_l) ). */
+void oracle_drift_second_order(const oracle_ctx *ctx, int k, int first, const double *L, double *b)
+{
+    const oracle_model *m = &ctx->m;
+    const int N = m->n_rates;
+    const double *lam = m->vol + (size_t)k * N;
+    double ell[64];
+    for (int l = first; l < N; ++l)
+        ell[l] = m->delta[l] * L[l] / (1.0 + m->delta[l] * L[l]);
+    oracle_drift_first_order(ctx, k, first, L, b);
+    for (int i = first; i < N; ++i) {
+        const double li = lam[i];
+        double second = 0.0;
+        for (int kk = i + 1; kk < N; ++kk)
+            for (int l = kk + 1; l < N; ++l) {
+                const double lk = lam[kk], ll = lam[l];
+                const double bracket = cumulant(ctx, li + lk + ll) - cumulant(ctx, li + lk)
+                                       - cumulant(ctx, li + ll) - cumulant(ctx, lk + ll)
+                                       + cumulant(ctx, li) + cumulant(ctx, lk) + cumulant(ctx, ll);
+                second += ell[kk] * ell[l] * bracket;
+            }
+        b[i] -= second;
+    }
+}
+
 /* ---------------- set-up ---------------- */
 
 oracle_ctx *oracle_create(const oracle_model *model)
@@ -316,6 +348,9 @@ static void simulate_path(const oracle_ctx *ctx, int scheme, int64_t p, double *
             } else if (scheme == ORACLE_FIRST_ORDER) {
                 for (int i = mth; i < N; ++i) L[i] = m->L0[i] * exp(X[i]);
                 oracle_drift_first_order(ctx, k, mth, L, b);
+            } else if (scheme == ORACLE_SECOND_ORDER) {
+                for (int i = mth; i < N; ++i) L[i] = m->L0[i] * exp(X[i]);
+                oracle_drift_second_order(ctx, k, mth, L, b);
             } else if (scheme == ORACLE_PICARD) {
                 for (int i = mth; i < N; ++i) L[i] = m->L0[i] * exp(X1[i]);
                 oracle_drift(ctx, k, mth, L, b);

@@ -5,7 +5,9 @@ The computation lives in the HIP library ``liblll.so`` behind the C ABI of
 package does not load the library; the first call does, and raises if the
 library is missing.
 """
-from ._lib import (FIRST_ORDER, FP32, FP64, FROZEN, FULL, PICARD, Batch, LLLError, Mlp, Plan,  # noqa: F401
-                   caplet_greeks, load, philox, price_caplets, version)
+from ._lib import (FIRST_ORDER, FP32, FP64, FROZEN, FULL, PICARD, SECOND_ORDER,  # noqa: F401
+                   Batch, LLLError, Mlp, Plan, caplet_greeks, load, philox, price_caplets,
+                   version)
 
-SCHEMES = {"full": FULL, "picard": PICARD, "frozen": FROZEN, "first_order": FIRST_ORDER}
+SCHEMES = {"full": FULL, "picard": PICARD, "frozen": FROZEN, "first_order": FIRST_ORDER,
+           "second_order": SECOND_ORDER}

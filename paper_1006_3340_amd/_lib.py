@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "liblll.so")
 LLL_OK = 0
 STATUS = {0: "LLL_OK", -1: "LLL_EINVAL", -2: "LLL_EMOMENT", -3: "LLL_ENOMEM", -4: "LLL_EHIP",
           -5: "LLL_EUNSUPPORTED", -6: "LLL_ENUMERIC"}
-FULL, PICARD, FROZEN, FIRST_ORDER = 0, 1, 2, 3
+FULL, PICARD, FROZEN, FIRST_ORDER, SECOND_ORDER = 0, 1, 2, 3, 4
 FP32, FP64 = 0, 1
 N_MAX, N_MAX_FP64, S_MAX, Q = 40, 24, 8, 64
 

@@ -263,8 +263,7 @@ int lll_plan_destroy(lll_plan *plan) {
 int lll_plan_execute(lll_plan *plan, int scheme, int64_t n_paths, int64_t path_offset,
                      uint64_t seed, double *path_fix_dev, void *stream) {
     if (!plan) return fail(LLL_EINVAL, "plan is NULL");
-    if (scheme != LLL_FULL && scheme != LLL_PICARD && scheme != LLL_FROZEN &&
-        scheme != LLL_FIRST_ORDER)
+    if (scheme < LLL_FULL || scheme > LLL_SECOND_ORDER)
         return fail(LLL_EINVAL, "unknown scheme %d", scheme);
     if (n_paths < 1 || n_paths > plan->max_paths)
         return fail(LLL_EINVAL, "n_paths=%lld outside 1..%lld", (long long)n_paths,

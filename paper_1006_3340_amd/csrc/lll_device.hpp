@@ -15,7 +15,7 @@ constexpr int kBlock = 256;     // threads per path block (4 wavefronts)
 constexpr double kTailExponent = 36.0;  // truncate the Lévy integral where e^{-36}
 constexpr double kXCap = 40.0;          // ... but never beyond |x| = 40
 
-enum { kFull = 0, kPicard = 1, kFrozen = 2, kFirst = 3 };
+enum { kFull = 0, kPicard = 1, kFrozen = 2, kFirst = 3, kSecond = 4 };
 enum { kNig = 0, kBrownian = 1 };
 
 // Philox-4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds of two

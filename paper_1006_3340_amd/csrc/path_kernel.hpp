@@ -129,8 +129,40 @@ __device__ __forceinline__ void first_order_coupling(cptr<Real> k2k, const Real 
     }
 }
 
+// Second-order expansion of the coupling (Section 3.2, eq. (drifta2)): the
+// product prod_{l>i}(1 + ell_l E_l) truncated after its terms of degree 2 in
+// ell, e1 + e2 (elementary symmetric sums of the ell_l E_l, l > i), integrated
+// with the same 64-node rule.  Per node, from the top slot down, with
+// u = 1 + e1 and s = e1 + e2 of the slots above j:
+//     C_j += W E_j s,   t = ell_j E_j,   s += t u,   u += t.
+template <typename Real, int NMAX, int J0>
+__device__ __forceinline__ void quad_coupling2(cptr<Real> row, const Real (&ell)[NMAX],
+                                               Real (&C)[NMAX]) {
+#pragma unroll
+    for (int j = J0; j < NMAX; ++j) C[j] = Real(0);
+    if constexpr (J0 < NMAX - 1) {
+        for (int q = 0; q < kQ; ++q, row += NMAX * 2) {
+            Real t = ell[NMAX - 1] * row[2 * (NMAX - 1)];
+            Real s = t;
+            Real u = Real(1) + t;
+#pragma unroll
+            for (int j = NMAX - 2; j >= J0; --j) {
+                const Real E = row[2 * j];
+                const Real WE = row[2 * j + 1];
+                C[j] = fma(WE, s, C[j]);
+                if (j > J0) {
+                    t = ell[j] * E;
+                    s = fma(t, u, s);
+                    u = u + t;
+                }
+            }
+        }
+    }
+}
+
 // Coupling sums of the scheme: the first-order expansion, the Brownian
-// closed form or the 64-node quadrature.
+// closed form (exact, hence also the second-order expansion), the truncated
+// product or the full product on the 64-node rule.
 template <typename Real, int NMAX, int SCHEME, int J0>
 __device__ __forceinline__ void coupling(const PathArgs<Real> &a, int k, const Real (&ell)[NMAX],
                                          Real (&C)[NMAX]) {
@@ -138,6 +170,8 @@ __device__ __forceinline__ void coupling(const PathArgs<Real> &a, int k, const R
         first_order_coupling<Real, NMAX, J0>(a.k2 + (size_t)k * NMAX * NMAX, ell, C);
     else if (a.brownian)
         brownian_coupling<Real, NMAX, J0>(a.lam + (size_t)k * NMAX, static_cast<Real>(a.c), ell, C);
+    else if constexpr (SCHEME == kSecond)
+        quad_coupling2<Real, NMAX, J0>(a.ew + (size_t)k * kQ * NMAX * 2, ell, C);
     else
         quad_coupling<Real, NMAX, J0>(a.ew + (size_t)k * kQ * NMAX * 2, ell, C);
 }
@@ -448,6 +482,9 @@ hipError_t launch_paths_n(const PathArgs<Real> &a, int scheme, int64_t n_paths, 
             break;
         case kFirst:
             hipLaunchKernelGGL((path_kernel<Real, NMAX, kFirst>), grid, dim3(kBlock), 0, st, a);
+            break;
+        case kSecond:
+            hipLaunchKernelGGL((path_kernel<Real, NMAX, kSecond>), grid, dim3(kBlock), 0, st, a);
             break;
         default:
             hipLaunchKernelGGL((path_kernel<Real, NMAX, kFrozen>), grid, dim3(kBlock), 0, st, a);

@@ -25,8 +25,8 @@ import workloads
 
 pytestmark = pytest.mark.gpu
 
-FULL, PICARD, FROZEN, FIRST_ORDER = 0, 1, 2, 3
-SCHEMES = (FULL, PICARD, FROZEN, FIRST_ORDER)
+FULL, PICARD, FROZEN, FIRST_ORDER, SECOND_ORDER = 0, 1, 2, 3, 4
+SCHEMES = (FULL, PICARD, FROZEN, FIRST_ORDER, SECOND_ORDER)
 
 
 def _oracle(oracle_mod, ts, seed=1):
