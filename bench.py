@@ -214,6 +214,34 @@ def bench_reference_schemes(lll, plan, ts, n, stream) -> dict:
     return out
 
 
+# Section 4 of the paper (Kluge's example, 10^4 paths, 5 steps per period):
+# implied-volatility errors against the full solution, basis points.
+PAPER_KLUGE_BP = {"picard": {"max": 0.023}, "frozen": {"max": 17.0},
+                  "first_order": {"max": 9.5, "mean": 0.41},
+                  "second_order": {"max": 0.38, "mean": 0.013}}
+
+
+def bench_kluge(lll, stream) -> dict:
+    """The paper's numerical example on the GPU (FP64 kernels): caplet
+    implied-volatility differences of each scheme against FULL (strikes
+    0.8..1.2 x forward), at the paper's 10^4 paths and at 2^20 paths, next to
+    the numbers the paper reports (its strike grid and random numbers differ)."""
+    from paper_1006_3340_amd import quotes
+    ts = workloads.kluge_example()
+    out = {"workload": ts.name, "strikes": "0.8..1.2 x forward", "paper_bp": PAPER_KLUGE_BP}
+    names = {1: "picard", 2: "frozen", 3: "first_order", 4: "second_order"}
+    for n in (10000, 1 << 20):
+        with lll.Plan(ts, precision=lll.FP64, max_paths=n) as plan:
+            iv = {}
+            for s in range(5):
+                plan.execute(s, n, seed=1, stream=stream)
+                iv[s] = quotes.caplet_implied_vols(ts, plan.results(stream)["price"])
+        out[f"paths_{n}"] = {names[s]: {"max_bp": float(np.nanmax(np.abs(iv[s] - iv[0]) * 1e4)),
+                                        "mean_bp": float(np.nanmean(np.abs(iv[s] - iv[0]) * 1e4))}
+                             for s in names}
+    return out
+
+
 def bench_batched(lll, stream, schemes, n_each: int = 1 << 18, reps: int = 2) -> dict:
     """64 independent structures in one persistent launch: kernel time (HIP events
     recorded by the library), path-steps/s and FP32 fraction of peak."""
@@ -250,6 +278,8 @@ def main(argv=None) -> int:
                     help="also time the pathwise Greeks pass (N=40, 2^20 paths)")
     ap.add_argument("--mlp", type=int, default=1,
                     help="also train the drift surrogate and time it (N=40, 2^20 paths)")
+    ap.add_argument("--kluge", type=int, default=1,
+                    help="also reproduce the paper's example (implied-volatility errors, FP64)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (a kernel of "
                          "known traffic for calibrating HBM counters)")
@@ -351,6 +381,8 @@ def main(argv=None) -> int:
         out["adjoint"] = bench_adjoint(lll, stream)
     if args.mlp:
         out["mlp"] = bench_mlp(lll, stream)
+    if args.kluge:
+        out["kluge"] = bench_kluge(lll, stream)
     if args.cpu_sample > 0:
         out["cpu_baseline"] = cpu_baseline(ts, args.cpu_sample, schemes)
     plan.close()
