@@ -242,6 +242,27 @@ def bench_kluge(lll, stream) -> dict:
     return out
 
 
+def bench_swaptions(lll, stream, n: int = 1 << 20) -> dict:
+    """Co-terminal payer swaptions on the benchmark workload (strikes 0.8, 1, 1.2
+    x forward swap rate): path-kernel time per scheme (the multi-rate payoff is
+    evaluated at each fixing date) and max relative error against FULL."""
+    ts = workloads.coterminal_swaptions(workloads.gpu_scale(), [0.8, 1.0, 1.2])
+    out = {"workload": ts.name}
+    with lll.Plan(ts, precision=lll.FP32, max_paths=n) as plan:
+        plan.set_timing(True)
+        prices = {}
+        for name in ("full", "picard", "first_order"):
+            plan.execute(lll.SCHEMES[name], n, seed=1, stream=stream)   # warmup
+            plan.execute(lll.SCHEMES[name], n, seed=1, stream=stream)
+            ms = plan.timing()["paths"]
+            prices[name] = plan.results(stream)["price"]
+            out[name] = {"path_kernel_ms": ms, "path_steps_per_s": n * ts.n_steps / (ms / 1e3)}
+    live = prices["full"] > 0.0
+    for name in prices:
+        out[name]["max_rel_err_vs_full"] = float(np.max(np.abs(prices[name][live] / prices["full"][live] - 1)))
+    return out
+
+
 def bench_batched(lll, stream, schemes, n_each: int = 1 << 18, reps: int = 2) -> dict:
     """64 independent structures in one persistent launch: kernel time (HIP events
     recorded by the library), path-steps/s and FP32 fraction of peak."""
@@ -375,6 +396,7 @@ def main(argv=None) -> int:
         "wall_s": wall,
     }
     out["reference_schemes"] = bench_reference_schemes(lll, plan, ts, n, stream)
+    out["swaptions"] = bench_swaptions(lll, stream)
     if args.batched:
         out["batched"] = bench_batched(lll, stream, schemes)
     if args.adjoint:

@@ -70,6 +70,17 @@ typedef enum {
     LLL_ENUMERIC = -6      /* non-finite payoffs were produced */
 } lll_status;
 
+/* Products priced at every fixing date T_i (rate r = i - 1 fixes at tenor[r]),
+ * strikes[r][j] absolute:
+ *   LLL_CAPLETS    delta_r B(0,T_*) E[ prod_{l>r}(1 + delta_l L_l(T_i)) (L_r(T_i) - K)^+ ]
+ *                  (Section 3.3, eq. (caplet));
+ *   LLL_SWAPTIONS  co-terminal payer swaptions: expiry T_i, underlying swap over
+ *                  the accrual periods r..N-1 (to T_*), paid in units of the
+ *                  terminal bond:
+ *                  B(0,T_*) E[ ( sum_{l>=r} delta_l (L_l(T_i) - K) prod_{j>l}(1 + delta_j L_j(T_i)) )^+ ].
+ * Results have the same [N][S] layout; n_itm counts positive payoffs. */
+typedef enum { LLL_CAPLETS = 0, LLL_SWAPTIONS = 1 } lll_product;
+
 typedef enum {
     LLL_FULL = 0,
     LLL_PICARD = 1,
@@ -91,7 +102,7 @@ typedef struct {
     int32_t n_strikes;          /* S, 1..LLL_S_MAX */
     int32_t driver;             /* lll_driver */
     uint32_t struct_id;         /* fourth Philox counter word (low 24 bits) */
-    int32_t reserved;
+    int32_t product;            /* lll_product: what the strikes price */
     const double *tenor;        /* [N] T_1..T_N, strictly increasing, > 0 */
     const double *delta;        /* [N] accrual fractions, > 0, matching tenor gaps */
     const double *L0;           /* [N] L(0, T_i) > 0 */
@@ -166,7 +177,8 @@ int lll_price_caplets(const lll_term_structure *ts, int64_t n_paths, int scheme,
 /* ---- pathwise adjoint (caplet Greeks) ---- */
 
 /* Enqueue a FULL-scheme pricing pass of paths 0 .. n_paths-1 on an FP32 plan
- * (NIG driver) together with the pathwise adjoint of every caplet price
+ * (NIG driver, LLL_CAPLETS; LLL_EUNSUPPORTED otherwise) together with the
+ * pathwise adjoint of every caplet price
  * (strike 0) with respect to the initial forwards L(0, T_l) and to a parallel
  * shift of each rate's volatility curve lambda(., T_l) (all steps k).  The
  * forward pass checkpoints the live rates at every tenor date; each caplet's

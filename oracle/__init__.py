@@ -51,6 +51,8 @@ class _Model(ctypes.Structure):
         ("n_nodes", ctypes.c_int32),
         ("stream_word", ctypes.c_uint32),
         ("seed", ctypes.c_uint64),
+        ("product", ctypes.c_int32),
+        ("pad", ctypes.c_int32),
         ("tenor", ctypes.POINTER(ctypes.c_double)),
         ("delta", ctypes.POINTER(ctypes.c_double)),
         ("L0", ctypes.POINTER(ctypes.c_double)),
@@ -161,6 +163,7 @@ class Oracle:
         m.n_nodes = len(self.x) if ts.driver == NIG else 0
         m.stream_word = (int(ts.struct_id) & 0xFFFFFF) | ((int(tag) & 0xFF) << 24)
         m.seed = self.seed
+        m.product = int(getattr(ts, "product", 0))
         m.tenor, m.delta, m.L0 = _dp(self._tenor), _dp(self._delta), _dp(self._L0)
         m.vol, m.strikes = _dp(self._vol), _dp(self._strikes)
         m.x, m.w = _dp(self.x), _dp(self.W)
@@ -249,14 +252,17 @@ class Oracle:
     def price(self, scheme: int, n_paths: int, path0: int = 0, threads: int = 0) -> dict:
         """Caplet prices, standard errors and martingale residuals (eq. (caplet))."""
         sums = self.price_sums(scheme, n_paths, path0, threads)
-        return finish(sums, self._delta, self._L0, self.B0_Tstar())
+        return finish(sums, self._delta, self._L0, self.B0_Tstar(),
+                      swaptions=int(getattr(self.ts, "product", 0)) == 1)
 
 
-def finish(sums: dict, delta: np.ndarray, L0: np.ndarray, B0_Tstar: float) -> dict:
-    """Prices delta_i B(0,T_*) mean(payoff), standard errors and martingale residuals
+def finish(sums: dict, delta: np.ndarray, L0: np.ndarray, B0_Tstar: float,
+           swaptions: bool = False) -> dict:
+    """Prices delta_i B(0,T_*) mean(payoff) (swaptions: B(0,T_*) mean(payoff)),
+    standard errors and martingale residuals
     mean(prod_{l>=i}(1 + delta_l L_l)) - prod_{l>=i}(1 + delta_l L(0,T_l))."""
     n = sums["n_paths"]
-    scale = (delta * B0_Tstar)[:, None]
+    scale = (np.ones_like(delta) if swaptions else delta)[:, None] * B0_Tstar
     mean = sums["sum_p"] / n
     var = np.maximum(sums["sum_p2"] / n - mean * mean, 0.0)
     se = scale * np.sqrt(var / max(n - 1, 1))

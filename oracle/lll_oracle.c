@@ -31,6 +31,12 @@
  *     (drifta)), in closed form through kappa;
  *   - the caplet payoff under the terminal measure (Section 3.3, eq. (caplet)):
  *       delta_i B(0,T_*) E[ prod_{l>i} (1 + delta_l L(T_i,T_l)) (L(T_i,T_i) - K)^+ ];
+ *     or, for co-terminal payer swaptions (a multi-rate product the paper
+ *     names as covered by the framework), expiring at T_i on the swap over
+ *     the periods i..N,
+ *       B(0,T_*) E[ ( sum_{l>=i} delta_l (L(T_i,T_l) - K) prod_{j>l} (1 + delta_j L(T_i,T_j)) )^+ ],
+ *     the value at T_i of the swap's payments B(T_i,T_{l+1}) / B(T_i,T_*) =
+ *     prod_{j>l} (1 + delta_j L(T_i,T_j)) in units of the terminal bond;
  *     this file returns path sums; the Python wrapper forms prices.
  *
  * Random numbers: the paper draws NIG increments "by the standard method"
@@ -59,6 +65,9 @@
 #define ORACLE_NIG 0
 #define ORACLE_BROWNIAN 1
 
+#define ORACLE_CAPLETS 0
+#define ORACLE_SWAPTIONS 1
+
 typedef struct {
     int32_t n_rates;          /* N */
     int32_t steps_per_period; /* s */
@@ -67,6 +76,8 @@ typedef struct {
     int32_t n_nodes;          /* Q (0 for the Brownian driver) */
     uint32_t stream_word;     /* fourth Philox counter word */
     uint64_t seed;            /* Philox key */
+    int32_t product;          /* ORACLE_CAPLETS or ORACLE_SWAPTIONS */
+    int32_t pad;
     const double *tenor;      /* T_1..T_N */
     const double *delta;      /* delta_1..delta_N */
     const double *L0;         /* L(0, T_i) */
@@ -328,8 +339,13 @@ const double *oracle_dt_table(const oracle_ctx *ctx) { return ctx->dt; }
 
 /* Simulates path p.  For every caplet i (fixing at T_i) writes the fixed rate
  * Lfix[i] = L(T_i, T_i) and the terminal-measure factor
- * Dfix[i] = prod_{l>i} (1 + delta_l L(T_i, T_l)) of the scheme's rates. */
-static void simulate_path(const oracle_ctx *ctx, int scheme, int64_t p, double *Lfix, double *Dfix)
+ * Dfix[i] = prod_{l>i} (1 + delta_l L(T_i, T_l)) of the scheme's rates; if
+ * Sfix / Afix are not NULL, also the floating and fixed legs of the
+ * co-terminal swap at T_i in units of B(T_i, T_*), term by term:
+ *   Sfix[i] = sum_{l>=i} delta_l L(T_i,T_l) prod_{j>l} (1 + delta_j L(T_i,T_j)),
+ *   Afix[i] = sum_{l>=i} delta_l prod_{j>l} (1 + delta_j L(T_i,T_j)). */
+static void simulate_path(const oracle_ctx *ctx, int scheme, int64_t p, double *Lfix, double *Dfix,
+                          double *Sfix, double *Afix)
 {
     const oracle_model *m = &ctx->m;
     const int N = m->n_rates, s = m->steps_per_period;
@@ -371,6 +387,17 @@ static void simulate_path(const oracle_ctx *ctx, int scheme, int64_t p, double *
             D *= 1.0 + m->delta[l] * m->L0[l] * exp(X[l]);
         Lfix[c] = Lc;
         Dfix[c] = D;
+        if (Sfix && Afix) {
+            double fl = 0.0, fx = 0.0;
+            for (int l = c; l < N; ++l) {
+                double Q = 1.0;
+                for (int j = l + 1; j < N; ++j) Q *= 1.0 + m->delta[j] * m->L0[j] * exp(X[j]);
+                fl += m->delta[l] * m->L0[l] * exp(X[l]) * Q;
+                fx += m->delta[l] * Q;
+            }
+            Sfix[c] = fl;
+            Afix[c] = fx;
+        }
     }
 }
 
@@ -379,7 +406,7 @@ int oracle_paths(const oracle_ctx *ctx, int scheme, const int64_t *paths, int64_
 {
     const int N = ctx->m.n_rates;
     for (int64_t j = 0; j < n; ++j)
-        simulate_path(ctx, scheme, paths[j], Lfix + j * N, Dfix + j * N);
+        simulate_path(ctx, scheme, paths[j], Lfix + j * N, Dfix + j * N, NULL, NULL);
     return 0;
 }
 
@@ -407,18 +434,21 @@ int oracle_price_sums(const oracle_ctx *ctx, int scheme, int64_t p0, int64_t n, 
         tid = omp_get_thread_num();
 #endif
         double *a = acc + (size_t)tid * (3 * NS + 2 * N);
-        double Lfix[64], Dfix[64];
+        double Lfix[64], Dfix[64], Sfix[64], Afix[64];
+        const int swaptions = ctx->m.product == ORACLE_SWAPTIONS;
         /* contiguous static chunk per thread: fixed summation order */
         int64_t lo = p0 + n * tid / nt, hi = p0 + n * (tid + 1) / nt;
         for (int64_t p = lo; p < hi; ++p) {
-            simulate_path(ctx, scheme, p, Lfix, Dfix);
+            simulate_path(ctx, scheme, p, Lfix, Dfix, swaptions ? Sfix : NULL,
+                          swaptions ? Afix : NULL);
             for (int c = 0; c < N; ++c) {
                 for (int r = 0; r < S; ++r) {
                     double K = ctx->m.strikes[(size_t)c * S + r];
-                    double pay = Dfix[c] * (Lfix[c] > K ? Lfix[c] - K : 0.0);
+                    double v = swaptions ? Sfix[c] - K * Afix[c] : Dfix[c] * (Lfix[c] - K);
+                    double pay = v > 0.0 ? v : 0.0;
                     a[(size_t)c * S + r] += pay;
                     a[NS + (size_t)c * S + r] += pay * pay;
-                    a[2 * NS + (size_t)c * S + r] += (Lfix[c] > K) ? 1.0 : 0.0;
+                    a[2 * NS + (size_t)c * S + r] += (v > 0.0) ? 1.0 : 0.0;
                 }
                 double mart = Dfix[c] * (1.0 + ctx->m.delta[c] * Lfix[c]);
                 a[3 * NS + c] += mart;

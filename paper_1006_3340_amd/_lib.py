@@ -20,6 +20,7 @@ LLL_OK = 0
 STATUS = {0: "LLL_OK", -1: "LLL_EINVAL", -2: "LLL_EMOMENT", -3: "LLL_ENOMEM", -4: "LLL_EHIP",
           -5: "LLL_EUNSUPPORTED", -6: "LLL_ENUMERIC"}
 FULL, PICARD, FROZEN, FIRST_ORDER, SECOND_ORDER = 0, 1, 2, 3, 4
+CAPLETS, SWAPTIONS = 0, 1
 FP32, FP64 = 0, 1
 N_MAX, N_MAX_FP64, S_MAX, Q = 40, 24, 8, 64
 
@@ -48,7 +49,7 @@ class TermStructureC(ctypes.Structure):
         ("n_strikes", ctypes.c_int32),
         ("driver", ctypes.c_int32),
         ("struct_id", ctypes.c_uint32),
-        ("reserved", ctypes.c_int32),
+        ("product", ctypes.c_int32),
         ("tenor", ctypes.POINTER(ctypes.c_double)),
         ("delta", ctypes.POINTER(ctypes.c_double)),
         ("L0", ctypes.POINTER(ctypes.c_double)),
@@ -165,6 +166,7 @@ class _TS:
         c.n_strikes = ts.n_strikes
         c.driver = int(ts.driver)
         c.struct_id = int(ts.struct_id) & 0xFFFFFFFF
+        c.product = int(getattr(ts, "product", 0))
         c.tenor, c.delta, c.L0, c.vol, c.strikes = [_dp(a) for a in self.arrays]
         c.B0_T1 = float(ts.B0_T1)
         c.alpha, c.beta, c.delta_nig, c.c = (float(ts.alpha), float(ts.beta),

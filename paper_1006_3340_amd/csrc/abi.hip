@@ -59,6 +59,8 @@ int validate(const lll_term_structure *ts) {
         return fail(LLL_EINVAL, "NULL input array");
     if (ts->driver != LLL_DRIVER_NIG && ts->driver != LLL_DRIVER_BROWNIAN)
         return fail(LLL_EINVAL, "unknown driver %d", ts->driver);
+    if (ts->product != LLL_CAPLETS && ts->product != LLL_SWAPTIONS)
+        return fail(LLL_EINVAL, "unknown product %d", ts->product);
     if (!finite_all(ts->tenor, N) || !finite_all(ts->delta, N) || !finite_all(ts->L0, N) ||
         !finite_all(ts->vol, (size_t)N * s * N) || !finite_all(ts->strikes, (size_t)N * S) ||
         !std::isfinite(ts->B0_T1))
@@ -156,6 +158,7 @@ int create_plan(const lll_term_structure *ts, int precision, int64_t max_paths, 
     p->nmax = nmax > 0 ? nmax : lll::bucket_for(p->N);
     p->off = p->nmax - p->N;
     p->struct_id = ts->struct_id;
+    p->product = ts->product;
     p->B0_T1 = ts->B0_T1 > 0.0 ? ts->B0_T1 : 1.0 / (1.0 + ts->tenor[0] * ts->L0[0]);
     p->alpha = ts->alpha;
     p->beta = ts->beta;
@@ -583,6 +586,8 @@ int lll_plan_greeks(lll_plan *plan, int64_t n_paths, uint64_t seed, void *stream
         return fail(LLL_EUNSUPPORTED, "the adjoint runs on FP32 plans");
     if (plan->driver != LLL_DRIVER_NIG)
         return fail(LLL_EUNSUPPORTED, "the adjoint is implemented for the NIG driver");
+    if (plan->product != LLL_CAPLETS)
+        return fail(LLL_EUNSUPPORTED, "the adjoint differentiates caplets");
     if (n_paths < 1 || n_paths > plan->max_paths)
         return fail(LLL_EINVAL, "n_paths=%lld outside 1..%lld", (long long)n_paths,
                     (long long)plan->max_paths);

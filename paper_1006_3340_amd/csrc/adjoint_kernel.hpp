@@ -112,7 +112,7 @@ __device__ void forward(const PathArgs<float> &a, const AdjArgs &g, int64_t gid,
             for (int j = 0; j < NMAX; ++j) xf = (j == j0) ? X[j] : xf;
             g.fix[static_cast<int64_t>(m) * g.n_paths + gid] = xf;
         }
-        detail::dispatch_payoff<float, NMAX>(std::make_integer_sequence<int, NMAX>{}, j0, a, m,
+        detail::dispatch_payoff<float, NMAX, LLL_CAPLETS>(std::make_integer_sequence<int, NMAX>{}, j0, a, m,
                                              gid, active, X);
     }
 }

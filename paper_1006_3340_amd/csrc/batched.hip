@@ -50,19 +50,28 @@ __global__ void __launch_bounds__(kBlock) batched_kernel(cptr<PathArgs<float>> a
                                                          cptr<BatchItem> items, int n_items,
                                                          int *__restrict__ counter) {
     // The block shares one item (its four wavefronts then stream the same
-    // step tables through the CU's scalar cache).
-    __shared__ int s_item;
+    // step tables through the CU's scalar cache).  With the state in LDS the
+    // item index travels through the first word of that array, which no
+    // simulation touches between the two barriers (so the block's LDS stays
+    // at 40 KiB: four blocks per CU).
+    int *slot;
+    if constexpr (detail::kStateInLds<float, kBatchSlots, SCHEME>) {
+        slot = reinterpret_cast<int *>(detail::state_lds<float, kBatchSlots>());
+    } else {
+        __shared__ int s_item;
+        slot = &s_item;
+    }
     for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+        if (threadIdx.x == 0) *slot = atomicAdd(counter, 1);
         __syncthreads();
-        const int item = __builtin_amdgcn_readfirstlane(s_item);
+        const int item = __builtin_amdgcn_readfirstlane(*slot);
         __syncthreads();
         if (item >= n_items) return;  // same value in every lane of the block
         const BatchItem it = load_uniform<BatchItem>(items + item);
         const PathArgs<float> a = load_uniform<PathArgs<float>>(args + it.s);
         const int64_t gid = it.first + threadIdx.x;
         const int64_t wave_first = gid - (threadIdx.x % kWave);
-        if (wave_first < a.n_paths) detail::simulate<float, kBatchSlots, SCHEME, false>(a, gid);
+        if (wave_first < a.n_paths) detail::simulate<float, kBatchSlots, SCHEME, true, detail::kAnyProduct>(a, gid);
     }
 }
 

@@ -65,6 +65,7 @@ struct GreeksBuffers {
 struct lll_plan {
     int N = 0, s = 0, S = 0, K = 0, driver = 0, precision = 0, nmax = 0, off = 0;
     uint32_t struct_id = 0;
+    int product = 0;  // lll_product
     double B0_T1 = 0, alpha = 0, beta = 0, delta_nig = 0, c = 0;
     int64_t max_paths = 0, max_waves = 0, max_chunks = 0;
     int device = 0;

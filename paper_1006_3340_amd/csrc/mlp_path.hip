@@ -332,7 +332,7 @@ mlp_path_kernel(PathArgs<float> a, MlpArgs g) {
         dispatch_finish(std::make_integer_sequence<int, kSlots>{}, j0, a, k, dH, need_quad, judge,
                         oob, C, X, st);
         if (++js == a.s) {
-            detail::dispatch_payoff<float, kSlots>(std::make_integer_sequence<int, kSlots>{}, j0, a,
+            detail::dispatch_payoff<float, kSlots, detail::kAnyProduct>(std::make_integer_sequence<int, kSlots>{}, j0, a,
                                                    m, gid, active, X);
             js = 0;
             ++m;

@@ -61,7 +61,7 @@ struct PathArgs {
     double *__restrict__ partials;     // [waves][N][NSTAT]
     double *__restrict__ path_fix;     // [n_paths][2N] or null
     int64_t n_paths, path_offset;
-    int N, s, S, off, brownian;
+    int N, s, S, off, brownian, product;
     uint32_t stream_word, key0, key1;
     double beta, c;
 };
@@ -203,11 +203,58 @@ __device__ __forceinline__ void step(const PathArgs<Real> &a, int k, Real dH, Re
     }
 }
 
-// Payoff of the caplet fixing at the end of period m (slot J0) and of the
-// martingale factor, summed over the wavefront; FP64 sums.
+// Wavefront sums (FP64) of the payoffs of the fixing of rate r, given
+// Q = prod_{l>=r}(1 + delta_l L_l), A = sum_{l>=r} delta_l prod_{j>l}(1 + delta_j L_j),
+// D = prod_{l>r}(1 + delta_l L_l) and L_r: per strike the sum, the sum of
+// squares and the count of positive payoffs, then the martingale factor Q.
+template <typename Real>
+__device__ __forceinline__ void fixing_sums(const PathArgs<Real> &a, int r, int64_t gid,
+                                            bool active, bool swaption, double Q, double A,
+                                            double D, double Lc) {
+    if (!swaption && a.path_fix != nullptr && active) {
+        a.path_fix[gid * 2 * a.N + 2 * r] = Lc;
+        a.path_fix[gid * 2 * a.N + 2 * r + 1] = D;
+    }
+    const int S = a.S;
+    double *out = a.partials + ((size_t)(gid / kWave) * a.N + r) * (3 * S + 2);
+    const bool lane0 = (threadIdx.x % kWave) == 0;
+    for (int t = 0; t < S; ++t) {
+        const double K = a.strikes[r * S + t];
+        const double v = swaption ? (Q - 1.0) - K * A : D * (Lc - K);
+        const double pay = active ? fmax(v, 0.0) : 0.0;
+        const double s1 = wave_sum(pay);
+        const double s2 = wave_sum(pay * pay);
+        const double ni = wave_sum((active && v > 0.0) ? 1.0 : 0.0);
+        if (lane0) {
+            out[t] = s1;
+            out[S + t] = s2;
+            out[2 * S + t] = ni;
+        }
+    }
+    const double M = active ? Q : 0.0;
+    const double m1 = wave_sum(M);
+    const double m2 = wave_sum(M * M);
+    if (lane0) {
+        out[3 * S] = m1;
+        out[3 * S + 1] = m2;
+    }
+}
+
+// Product of a kernel: LLL_CAPLETS or LLL_SWAPTIONS fixed at compile time (the
+// plain path kernels, so each carries only its own payoff code), or read from
+// the arguments (kAnyProduct: the batched and surrogate kernels).
+constexpr int kAnyProduct = -1;
+
+// Payoffs at the end of period m (the rate in slot J0 fixes), in units of the
+// terminal bond, and the martingale factor M = prod_{l>=c}(1 + delta_l L_l),
+// summed over the wavefront; FP64.  Caplets: D (L_c - K)^+ with
+// D = prod_{l>c}(1 + delta_l L_l).  Co-terminal payer swaptions: the swap's
+// value sum_{l>=c} delta_l (L_l - K) Q_l with Q_l = prod_{j>l}(1 + delta_j L_j);
+// its floating leg telescopes, sum_{l>=c} delta_l L_l Q_l = M - 1, and its
+// fixed leg is K A with A = sum_{l>=c} delta_l Q_l.
 template <typename Real, int NMAX, int J0>
-__device__ __forceinline__ void payoff(const PathArgs<Real> &a, int m, int64_t gid, bool active,
-                                       const Real (&X)[NMAX]) {
+__device__ __forceinline__ void caplet_payoff(const PathArgs<Real> &a, int m, int64_t gid,
+                                              bool active, const Real (&X)[NMAX]) {
     const int r = m;  // caplet on the rate with maturity T_{m+1}
     double D = 1.0;
 #pragma unroll
@@ -242,6 +289,57 @@ __device__ __forceinline__ void payoff(const PathArgs<Real> &a, int m, int64_t g
         out[3 * S] = m1;
         out[3 * S + 1] = m2;
     }
+}
+
+template <typename Real, int NMAX, int J0, int PRODUCT>
+__device__ __forceinline__ void payoff(const PathArgs<Real> &a, int m, int64_t gid, bool active,
+                                       const Real (&X)[NMAX]) {
+    if constexpr (PRODUCT == LLL_CAPLETS) {
+        caplet_payoff<Real, NMAX, J0>(a, m, gid, active, X);
+        return;
+    }
+    // Same arithmetic as payoff_lds (so the kernels that read the product at
+    // run time reproduce the LDS kernels bit for bit): one pass from the last
+    // rate down, Q = prod_{j>l}(1 + delta_j L_j) before slot l is multiplied
+    // in; D = Q at slot J0, M = Q at the end.
+    const int r = m;  // the rate with maturity T_{m+1}
+    const bool swaption =
+        PRODUCT == kAnyProduct ? a.product == LLL_SWAPTIONS : PRODUCT == LLL_SWAPTIONS;
+    double Q = 1.0, A = 0.0, D = 1.0, Lc = 0.0;
+#pragma unroll
+    for (int j = NMAX - 1; j >= J0; --j) {
+        const double L = a.L0s[j] * static_cast<double>(exp(X[j]));
+        if (j == J0) {
+            D = Q;
+            Lc = L;
+        }
+        A = fma(a.deltas[j], Q, A);
+        Q *= 1.0 + a.deltas[j] * L;
+    }
+    fixing_sums(a, r, gid, active, swaption, Q, A, D, Lc);
+}
+
+// Payoffs of the LDS-state kernels: the state is read from the thread's LDS
+// column slot by slot in a loop, so no register copy of all slots (whose
+// unrolled FP64 products would otherwise set the kernel's register count:
+// 86 -> 58 VGPRs for FULL at 24 slots).  Same quantities as payoff().
+template <typename Real, int NMAX, int PRODUCT>
+__device__ __forceinline__ void payoff_lds(const PathArgs<Real> &a, int m, int64_t gid,
+                                           bool active, const Real *xs, int j0) {
+    const int r = m;
+    const bool swaption =
+        PRODUCT == kAnyProduct ? a.product == LLL_SWAPTIONS : PRODUCT == LLL_SWAPTIONS;
+    double Q = 1.0, A = 0.0, D = 1.0, Lc = 0.0;
+    for (int j = NMAX - 1; j >= j0; --j) {
+        const double L = a.L0s[j] * static_cast<double>(exp(xs[j * kBlock]));
+        if (j == j0) {
+            D = Q;
+            Lc = L;
+        }
+        A = fma(a.deltas[j], Q, A);
+        Q *= 1.0 + a.deltas[j] * L;
+    }
+    fixing_sums(a, r, gid, active, swaption, Q, A, D, Lc);
 }
 
 // The same step with the state X held in LDS (column `xs`, stride kBlock) for
@@ -285,11 +383,11 @@ __device__ __forceinline__ void dispatch_step(std::integer_sequence<int, Js...>,
     (void)((j0 == Js ? (step<Real, NMAX, SCHEME, Js>(a, k, dH, X, X1), 0) : 0) + ...);
 }
 
-template <typename Real, int NMAX, int... Js>
+template <typename Real, int NMAX, int PRODUCT, int... Js>
 __device__ __forceinline__ void dispatch_payoff(std::integer_sequence<int, Js...>, int j0,
                                                 const PathArgs<Real> &a, int m, int64_t gid,
                                                 bool active, const Real (&X)[NMAX]) {
-    (void)((j0 == Js ? (payoff<Real, NMAX, Js>(a, m, gid, active, X), 0) : 0) + ...);
+    (void)((j0 == Js ? (payoff<Real, NMAX, Js, PRODUCT>(a, m, gid, active, X), 0) : 0) + ...);
 }
 
 // The block's LDS state, [slot][thread]: one allocation per kernel that uses it.
@@ -299,7 +397,7 @@ __device__ __forceinline__ Real *state_lds() {
     return sX;
 }
 
-template <typename Real, int NMAX, int SCHEME>
+template <typename Real, int NMAX, int SCHEME, int PRODUCT>
 __device__ __forceinline__ void simulate_lds(const PathArgs<Real> &a, int64_t gid) {
     Real *xs = state_lds<Real, NMAX>() + threadIdx.x;
     const bool active = gid < a.n_paths;
@@ -325,11 +423,7 @@ __device__ __forceinline__ void simulate_lds(const PathArgs<Real> &a, int64_t gi
         dispatch_step_lds<Real, NMAX, SCHEME>(std::make_integer_sequence<int, NMAX>{}, j0, a, k, dH,
                                               xs, X1);
         if (++js == a.s) {
-            Real X[NMAX];
-#pragma unroll
-            for (int j = 0; j < NMAX; ++j) X[j] = xs[j * kBlock];
-            dispatch_payoff<Real, NMAX>(std::make_integer_sequence<int, NMAX>{}, j0, a, m, gid,
-                                        active, X);
+            payoff_lds<Real, NMAX, PRODUCT>(a, m, gid, active, xs, j0);
             js = 0;
             ++m;
         }
@@ -348,12 +442,12 @@ constexpr bool kStateInLds = sizeof(Real) == 4 && NMAX >= 24 && SCHEME != kFroze
 // but contribute nothing) through all periods, writing the wave's payoff sums.
 // Every lane of the wavefront must call this together (wave reductions), and
 // every thread of the block index its own LDS column (threadIdx.x < kBlock).
-// ALLOW_LDS = false keeps the state in registers (the batched launch, whose
-// item loop leaves it at the same occupancy either way, is faster so).
-template <typename Real, int NMAX, int SCHEME, bool ALLOW_LDS = true>
+// ALLOW_LDS = false keeps the state in registers; PRODUCT is LLL_CAPLETS,
+// LLL_SWAPTIONS or kAnyProduct (see payoff).
+template <typename Real, int NMAX, int SCHEME, bool ALLOW_LDS, int PRODUCT>
 __device__ __forceinline__ void simulate(const PathArgs<Real> &a, int64_t gid) {
     if constexpr (ALLOW_LDS && kStateInLds<Real, NMAX, SCHEME>) {
-        simulate_lds<Real, NMAX, SCHEME>(a, gid);
+        simulate_lds<Real, NMAX, SCHEME, PRODUCT>(a, gid);
         return;
     }
     const bool active = gid < a.n_paths;
@@ -379,7 +473,7 @@ __device__ __forceinline__ void simulate(const PathArgs<Real> &a, int64_t gid) {
         dispatch_step<Real, NMAX, SCHEME>(std::make_integer_sequence<int, NMAX>{}, j0, a, k, dH, X,
                                           X1);
         if (++js == a.s) {
-            dispatch_payoff<Real, NMAX>(std::make_integer_sequence<int, NMAX>{}, j0, a, m, gid,
+            dispatch_payoff<Real, NMAX, PRODUCT>(std::make_integer_sequence<int, NMAX>{}, j0, a, m, gid,
                                         active, X);
             js = 0;
             ++m;
@@ -387,12 +481,12 @@ __device__ __forceinline__ void simulate(const PathArgs<Real> &a, int64_t gid) {
     }
 }
 
-template <typename Real, int NMAX, int SCHEME>
+template <typename Real, int NMAX, int SCHEME, int PRODUCT>
 __global__ void __launch_bounds__(kBlock) path_kernel(PathArgs<Real> a) {
     const int64_t gid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     const int64_t wave_first = gid - (threadIdx.x % kWave);
     if (wave_first >= a.n_paths) return;  // whole wavefront past the end
-    simulate<Real, NMAX, SCHEME>(a, gid);
+    simulate<Real, NMAX, SCHEME, true, PRODUCT>(a, gid);
 }
 
 // Drift of the live rates at step k for given rate vectors (inspection): the
@@ -462,6 +556,7 @@ inline PathArgs<Real> make_args(const lll_plan &p, uint64_t seed, int64_t n_path
     a.S = p.S;
     a.off = p.off;
     a.brownian = p.driver == LLL_DRIVER_BROWNIAN;
+    a.product = p.product;
     a.stream_word = p.struct_id & 0xFFFFFFu;
     a.key0 = static_cast<uint32_t>(seed & 0xFFFFFFFFull);
     a.key1 = static_cast<uint32_t>(seed >> 32);
@@ -470,26 +565,34 @@ inline PathArgs<Real> make_args(const lll_plan &p, uint64_t seed, int64_t n_path
     return a;
 }
 
+template <typename Real, int NMAX, int PRODUCT>
+void launch_scheme(const PathArgs<Real> &a, int scheme, dim3 grid, hipStream_t st) {
+    switch (scheme) {
+        case kFull:
+            hipLaunchKernelGGL((path_kernel<Real, NMAX, kFull, PRODUCT>), grid, dim3(kBlock), 0, st, a);
+            break;
+        case kPicard:
+            hipLaunchKernelGGL((path_kernel<Real, NMAX, kPicard, PRODUCT>), grid, dim3(kBlock), 0, st, a);
+            break;
+        case kFirst:
+            hipLaunchKernelGGL((path_kernel<Real, NMAX, kFirst, PRODUCT>), grid, dim3(kBlock), 0, st, a);
+            break;
+        case kSecond:
+            hipLaunchKernelGGL((path_kernel<Real, NMAX, kSecond, PRODUCT>), grid, dim3(kBlock), 0, st, a);
+            break;
+        default:
+            hipLaunchKernelGGL((path_kernel<Real, NMAX, kFrozen, PRODUCT>), grid, dim3(kBlock), 0, st, a);
+            break;
+    }
+}
+
 template <typename Real, int NMAX>
 hipError_t launch_paths_n(const PathArgs<Real> &a, int scheme, int64_t n_paths, hipStream_t st) {
     const dim3 grid(static_cast<unsigned>((n_paths + kBlock - 1) / kBlock));
-    switch (scheme) {
-        case kFull:
-            hipLaunchKernelGGL((path_kernel<Real, NMAX, kFull>), grid, dim3(kBlock), 0, st, a);
-            break;
-        case kPicard:
-            hipLaunchKernelGGL((path_kernel<Real, NMAX, kPicard>), grid, dim3(kBlock), 0, st, a);
-            break;
-        case kFirst:
-            hipLaunchKernelGGL((path_kernel<Real, NMAX, kFirst>), grid, dim3(kBlock), 0, st, a);
-            break;
-        case kSecond:
-            hipLaunchKernelGGL((path_kernel<Real, NMAX, kSecond>), grid, dim3(kBlock), 0, st, a);
-            break;
-        default:
-            hipLaunchKernelGGL((path_kernel<Real, NMAX, kFrozen>), grid, dim3(kBlock), 0, st, a);
-            break;
-    }
+    if (a.product == LLL_SWAPTIONS)
+        launch_scheme<Real, NMAX, LLL_SWAPTIONS>(a, scheme, grid, st);
+    else
+        launch_scheme<Real, NMAX, LLL_CAPLETS>(a, scheme, grid, st);
     return hipGetLastError();
 }
 

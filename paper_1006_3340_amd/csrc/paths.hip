@@ -84,7 +84,7 @@ __global__ void __launch_bounds__(256) reduce_rows_kernel(const double *__restri
 __global__ void __launch_bounds__(64) finalize_kernel(const double *__restrict__ sums,
                                                       const double *__restrict__ delta,
                                                       const double *__restrict__ L0, int N, int S,
-                                                      double B0_T1, int64_t n_paths,
+                                                      double B0_T1, int64_t n_paths, int product,
                                                       double *__restrict__ res) {
     const int nstat = 3 * S + 2;
     double prod_all = 1.0;
@@ -96,7 +96,8 @@ __global__ void __launch_bounds__(64) finalize_kernel(const double *__restrict__
     double *mart = res + 3 * N * S, *mart_se = res + 3 * N * S + N;
     for (int r = threadIdx.x; r < N; r += blockDim.x) {
         const double *sr = sums + (size_t)r * nstat;
-        const double scale = delta[r] * B0T;
+        // caplets pay delta_r (L - K)^+; swaption payoffs are already amounts
+        const double scale = product == LLL_SWAPTIONS ? B0T : delta[r] * B0T;
         for (int t = 0; t < S; ++t) {
             const double mean = sr[t] / n;
             const double var = fmax(sr[S + t] / n - mean * mean, 0.0);
@@ -178,7 +179,7 @@ hipError_t launch_reduce(const lll_plan &p, int64_t n_paths, hipStream_t st) {
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(64), 0, st, p.d.sums, p.d.delta, p.d.L0, p.N,
-                       p.S, p.B0_T1, n_paths, p.d.results);
+                       p.S, p.B0_T1, n_paths, p.product, p.d.results);
     return hipGetLastError();
 }
 

@@ -72,6 +72,9 @@ def test_validation_errors():
     _expect(EUNSUP, workloads.learned_drift(), precision=1)
     big = workloads.make_structure(41, 0.25, 0.03, 2, lambda t, T, r: 0.1, [1.0])
     _expect(EINVAL, big)
+    bad = ts.copy()
+    bad.product = 2                                       # neither caplets nor swaptions
+    _expect(EINVAL, bad)
 
 
 def test_inspection_entry_points_validate():

@@ -460,3 +460,57 @@ def test_autograd_function(gpu_lib):
     assert np.allclose(P.detach().numpy(), g["price"], rtol=0, atol=0)
     assert np.allclose(L0.grad.numpy(), w.numpy() @ g["dP_dL0"], rtol=1e-12)
     assert np.allclose(lv.grad.numpy(), w.numpy() @ g["dP_dvol"], rtol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Co-terminal payer swaptions (multi-rate payoff at every fixing date)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("wl,n_paths", [("plain_n10", 5000), ("gpu_n20", 2000), ("kluge_n9", 3001)])
+def test_swaptions_fp64_kernel_matches_oracle(gpu_lib, oracle_mod, wl, n_paths, scheme):
+    ts = workloads.coterminal_swaptions(workloads.WORKLOADS[wl](), [0.8, 1.0, 1.2])
+    ref = _oracle(oracle_mod, ts).price(scheme, n_paths)
+    with gpu_lib.Plan(ts, precision=1, max_paths=n_paths) as plan:
+        plan.execute(scheme, n_paths, seed=1)
+        got = plan.results()
+    assert np.array_equal(got["n_itm"], ref["n_itm"])
+    assert np.allclose(got["price"], ref["price"], rtol=1e-10, atol=1e-300)
+    assert np.allclose(got["mart_resid"], ref["mart_resid"], rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("wl,n_paths", [("gpu_n20", 4173), ("mlp_n40", 700)])
+def test_swaptions_fp32_kernel_matches_oracle(gpu_lib, oracle_mod, wl, n_paths):
+    ts = workloads.coterminal_swaptions(workloads.WORKLOADS[wl](), [0.8, 1.0, 1.2])
+    o = _oracle(oracle_mod, ts)
+    with gpu_lib.Plan(ts, precision=0, max_paths=n_paths) as plan:
+        for scheme in (FULL, PICARD, FIRST_ORDER):
+            ref = o.price(scheme, n_paths)
+            plan.execute(scheme, n_paths, seed=1)
+            _check_prices(plan.results(), ref, ts, 1e-4)
+
+
+def test_swaption_identities_on_gpu(gpu_lib):
+    """The last expiry's swaption is the last caplet (one-period swap); the
+    adjoint refuses swaption plans; batched and single launches agree."""
+    ts = workloads.gpu_scale()
+    sw = workloads.coterminal_swaptions(ts, [0.9, 1.0, 1.1])
+    cap = ts.copy(strikes=sw.strikes.copy())
+    n = 1 << 16
+    with gpu_lib.Plan(sw, precision=0, max_paths=n) as p1, \
+            gpu_lib.Plan(cap, precision=0, max_paths=n) as p2:
+        p1.execute(FULL, n, seed=4)
+        p2.execute(FULL, n, seed=4)
+        a, b = p1.results()["price"], p2.results()["price"]
+        assert np.allclose(a[-1], b[-1], rtol=1e-12, atol=0)
+        with pytest.raises(gpu_lib.LLLError) as ei:
+            p1.greeks(n, seed=1)
+        assert ei.value.code == -5
+    structs = [sw, workloads.coterminal_swaptions(workloads.plain_fp64(), [1.0])]
+    with gpu_lib.Batch(structs, max_paths_each=4096) as bt:
+        bt.execute(FULL, 4096, seed=2)
+        for i, s in enumerate(structs):
+            with gpu_lib.Plan(s, precision=0, max_paths=4096) as p:
+                p.execute(FULL, 4096, seed=2)
+                assert np.allclose(bt.results(i)["price"], p.results()["price"], rtol=1e-6,
+                                   atol=1e-300)

@@ -159,3 +159,36 @@ def test_kluge_example_against_the_papers_reported_errors(oracle_mod):
     assert 1.0 < mx[2] < 100.0                           # paper: ~17 bp
     assert 0.04 < mean[3] < 4.0 and 0.5 < mx[3] < 50.0   # paper: 0.41 / 9.5 bp
     assert 0.0013 < mean[4] < 0.13 and mx[4] < 1.0       # paper: 0.013 / 0.38 bp
+
+
+def test_swaptions_pins(oracle_mod):
+    """Co-terminal payer swaptions: the last expiry is a one-period swap, i.e.
+    the last caplet; without volatility the price is the discounted intrinsic
+    value from bond prices; a zero strike makes the payoff the floating leg
+    B(T_i, T_i) / B(T_i, T_*) - 1, whose price is B(0, T_i) - B(0, T_*) up to
+    Monte Carlo and Euler error (martingale property of the bond ratios)."""
+    ts = workloads.plain_fp64()
+    sw = workloads.coterminal_swaptions(ts, [0.0, 0.9, 1.0, 1.1])
+    cap = ts.copy(strikes=np.repeat(sw.strikes[:, 1:2], 1, axis=1))
+    n = 20000
+    for scheme in (0, 1, 2):
+        a = oracle_mod.Oracle(sw).price(scheme, n)
+        b = oracle_mod.Oracle(cap).price(scheme, n)
+        assert abs(a["price"][-1, 1] - b["price"][-1, 0]) <= 1e-14 * b["price"][-1, 0]
+    # zero volatility
+    z = workloads.coterminal_swaptions(
+        workloads.make_structure(7, 0.5, 0.03 + 0.004 * np.arange(7), 3, lambda t, T, r: 0.0,
+                                 [1.0]), [0.8, 1.0, 1.2])
+    P = z.B0_T1 / np.concatenate([[1.0], np.cumprod(1.0 + z.delta * z.L0)])
+    ann = np.cumsum((z.delta * P[1:])[::-1])[::-1]
+    exact = np.maximum(P[:-1, None] - P[-1] - z.strikes * ann[:, None], 0.0)
+    got = oracle_mod.Oracle(z).price(0, 50)["price"]
+    # (at the money forward the intrinsic value is 0 up to the rounding of a
+    # difference of O(1) bond prices)
+    assert np.allclose(got, exact, rtol=1e-12, atol=1e-14)
+    assert np.all(exact[:, 1] < 1e-15)
+    # zero strike under FULL: B(0,T_i) - B(0,T_*)
+    r = oracle_mod.Oracle(sw).price(0, n)
+    P = sw.B0_T1 / np.concatenate([[1.0], np.cumprod(1.0 + sw.delta * sw.L0)])
+    target = P[:-1] - P[-1]
+    assert np.all(np.abs(r["price"][:, 0] - target) <= 4 * r["stderr"][:, 0] + 1e-6 * target)

@@ -56,6 +56,7 @@ class TermStructure:
     c: float = 0.0             # Brownian variance rate (driver == BROWNIAN)
     struct_id: int = 0         # fourth Philox counter word (low 24 bits)
     name: str = ""
+    product: int = 0           # 0: caplets; 1: co-terminal payer swaptions
 
     @property
     def n_rates(self) -> int:
@@ -225,6 +226,27 @@ def kluge_example(steps_per_period: int = 5, strike_mult=(0.8, 0.9, 1.0, 1.1, 1.
                           lambda t, T, r: float(vols[r]), list(strike_mult),
                           alpha=1.5, beta=0.0, delta_nig=1.5, B0_T1=float(B[0]),
                           name="kluge_n9")
+
+
+def swap_rates(ts: TermStructure) -> np.ndarray:
+    """Forward co-terminal swap rates S_r(0) = (B(0,T_{r+1}) - B(0,T_*)) /
+    sum_{l>=r} delta_l B(0,T_{l+2}) from the initial forwards (bond prices by
+    eq. (i-val))."""
+    P = ts.B0_T1 / np.concatenate([[1.0], np.cumprod(1.0 + ts.delta * ts.L0)])  # B(0,T_1..T_*)
+    ann = np.cumsum((ts.delta * P[1:])[::-1])[::-1]
+    return (P[:-1] - P[-1]) / ann
+
+
+def coterminal_swaptions(ts: TermStructure, strike_mult=(0.8, 1.0, 1.2)) -> TermStructure:
+    """The same model pricing payer swaptions instead of caplets: expiry at
+    each fixing date T_{r+1}, underlying swap over the accrual periods r..N-1
+    (to T_*), strikes strike_mult x the forward swap rate."""
+    mult = np.atleast_1d(np.asarray(strike_mult, dtype=np.float64))
+    out = ts.copy(strikes=swap_rates(ts)[:, None] * mult[None, :])
+    out.product = 1
+    out.name = ts.name + "_swaptions"
+    out.validate_shapes()
+    return out
 
 
 def brownian(N: int = 6, delta: float = 0.5, L0=0.05, vol=0.2, c: float = 1.0,
