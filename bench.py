@@ -50,20 +50,25 @@ METRIC = "path-steps/s: full Euler vs Picard vs MLP drift, at <=1e-4 rel caplet 
 
 
 def flops_per_path_step(scheme: str, n: int) -> int:
-    """Algorithmic FP32 flops of one Euler step with n live rates (FMA = 2):
-    suffix recursion 6 per (rate, node) pair over n-1 couplings, plus Q for the
-    top rate, 8 per rate for ell and the update (16 for Picard, which also
-    advances its predictor), 40 for the increment."""
+    """Algorithmic FP32 flops of one Euler step with n live rates (FMA = 2).
+    FULL / PICARD, per quadrature node: the top rate's R = ell E (1), the n - 1
+    coupled rates' C += W E R (2 each) and the n - 2 rates between them and
+    the lowest live rate advancing R = R + ell E (1 + R) (4 each), i.e.
+    6n - 9 per node; plus 8 per rate for ell and the update (16 for PICARD,
+    which also advances its predictor) and 40 for the increment.
+    SECOND_ORDER: 6n - 8 per node (the truncated product carries two sums).
+    FIRST_ORDER: n (n - 1) / 2 FMAs of the closed-form sums.  FROZEN: the update."""
+    node = Q * (6 * n - 9) if n >= 2 else 0
     if scheme == "full":
-        return 6 * Q * (n - 1) + Q + 8 * n + 40
+        return node + 8 * n + 40
     if scheme == "picard":
-        return 6 * Q * (n - 1) + Q + 16 * n + 40
+        return node + 16 * n + 40
     if scheme == "frozen":
         return 4 * n + 40
-    if scheme == "first_order":       # n (n - 1) / 2 FMAs of the closed-form sums
+    if scheme == "first_order":
         return n * (n - 1) + 8 * n + 40
-    if scheme == "second_order":      # 7 flops per (rate, node): C += W E s, t, s, u
-        return 7 * Q * (n - 1) + Q + 8 * n + 40
+    if scheme == "second_order":
+        return (Q * (6 * n - 8) if n >= 2 else 0) + 8 * n + 40
     raise ValueError(scheme)
 
 
