@@ -5,7 +5,7 @@
  * One call prices caplets (paper Section 3.3, eq. (caplet)) by simulating
  * log-LIBOR rates under the terminal measure P_{T_*} (Section 2, eqs.
  * (LIBOR-dyn-PT), (LIBOR-drift-PT), (log-LIB-SIE)) with an Euler scheme and
- * one of five drift treatments (Section 3):
+ * one of five drift treatments (Section 3), PICARD also in a second layout:
  *
  *   LLL_FULL    the drift of eq. (LIBOR-drift-PT) at the current rates;
  *   LLL_PICARD  the drift of eq. (bdrift), evaluated at the second Picard
@@ -19,6 +19,14 @@
  *               first-order bracket with the signs of eq. (drifta)); the
  *               truncated product is integrated with the 64-node rule;
  *               error O(|L|^3);
+ *   LLL_PICARD_MP    LLL_PICARD computed in a maturity-parallel layout: under
+ *               the Picard approximation the drift of every step depends on
+ *               the predictor path only (Section 3), so the drift integrals
+ *               of all accrual periods are computed at once, spread over
+ *               (group of 4 paths, period, quadrature node) instead of one
+ *               path per lane.  The same estimator as LLL_PICARD (equal up to
+ *               FP32 summation order) for runs with few paths and many rates;
+ *               FP32 plans, NIG driver, N up to LLL_N_MAX_MP.
  *
  * driven by a normal inverse Gaussian Lévy process (Section 4) or, as a
  * special case, by a Brownian motion.  The jump integral of the drift is the
@@ -54,7 +62,9 @@
 extern "C" {
 #endif
 
-#define LLL_N_MAX 40        /* largest number of rates N */
+#define LLL_N_MAX 40        /* largest N of the path-per-lane kernels (all schemes but
+                               LLL_PICARD_MP), of batches, Greeks and the surrogate */
+#define LLL_N_MAX_MP 64     /* largest N of a plan (N > LLL_N_MAX: LLL_PICARD_MP only) */
 #define LLL_N_MAX_FP64 24   /* largest N for the FP64 path kernel */
 #define LLL_S_MAX 8         /* largest number of strikes per caplet */
 #define LLL_Q 64            /* quadrature nodes of the coupling integral */
@@ -86,7 +96,8 @@ typedef enum {
     LLL_PICARD = 1,
     LLL_FROZEN = 2,
     LLL_FIRST_ORDER = 3,
-    LLL_SECOND_ORDER = 4
+    LLL_SECOND_ORDER = 4,
+    LLL_PICARD_MP = 5
 } lll_scheme;
 typedef enum { LLL_DRIVER_NIG = 0, LLL_DRIVER_BROWNIAN = 1 } lll_driver;
 typedef enum { LLL_FP32 = 0, LLL_FP64 = 1 } lll_precision;
@@ -97,7 +108,7 @@ typedef enum { LLL_FP32 = 0, LLL_FP64 = 1 } lll_precision;
  * (assumption (LR1)).  NIG driver: alpha > |beta|, delta_nig > 0, its drift
  * chosen so that H is a martingale; Brownian driver: c >= 0. */
 typedef struct {
-    int32_t n_rates;            /* N, 1..LLL_N_MAX */
+    int32_t n_rates;            /* N, 1..LLL_N_MAX_MP (see LLL_N_MAX) */
     int32_t steps_per_period;   /* s >= 1 */
     int32_t n_strikes;          /* S, 1..LLL_S_MAX */
     int32_t driver;             /* lll_driver */
@@ -134,7 +145,13 @@ int lll_plan_create(const lll_term_structure *ts, int precision, int64_t max_pat
  * allocated on its first use, LLL_ENOMEM if that fails); the path kernel over
  * paths path_offset .. path_offset + n_paths - 1; the deterministic FP64
  * reduction of the payoff sums.  Asynchronous: results are read with
- * lll_plan_results.  If path_fix_dev is not NULL it receives, for every path
+ * lll_plan_results.  LLL_PICARD_MP replaces the path kernel by three kernels
+ * (predictor and increments, per-period drift integrals, payoffs) over chunks
+ * of paths whose buffers (ell at the predictor for every step, rate and path:
+ * 4 K N bytes per path, plus 4 N^2) stay within 2 GiB; they are allocated on
+ * its first use (LLL_ENOMEM if that fails); LLL_EUNSUPPORTED on FP64 plans or
+ * the Brownian driver.  Plans with N > LLL_N_MAX run only LLL_PICARD_MP
+ * (LLL_EUNSUPPORTED for the other schemes).  If path_fix_dev is not NULL it receives, for every path
  * j of this call and caplet r, L(T_r, T_r) at [j][2r] and the terminal-measure
  * factor prod_{l>r}(1 + delta_l L(T_r, T_l)) at [j][2r+1] (FP64, n_paths x 2N). */
 int lll_plan_execute(lll_plan *plan, int scheme, int64_t n_paths, int64_t path_offset,
@@ -186,7 +203,8 @@ int lll_price_caplets(const lll_term_structure *ts, int64_t n_paths, int scheme,
  * B(0, T_1) is held fixed, so dP/dL0 includes the dependence of B(0, T_*) on
  * the forwards (paper Section 3.3, eq. (caplet)).  Checkpoint and scratch
  * buffers (about (N (N+1) / 2 + N + s nmax + s) x 4 bytes per path) are
- * allocated on the first call and kept by the plan.  Asynchronous. */
+ * allocated on the first call and kept by the plan.  LLL_EUNSUPPORTED for
+ * N > LLL_N_MAX.  Asynchronous. */
 int lll_plan_greeks(lll_plan *plan, int64_t n_paths, uint64_t seed, void *stream);
 
 /* Wait for `stream` and copy the last Greeks pass: price_host[N] (strike 0),
@@ -290,8 +308,8 @@ typedef struct lll_batch lll_batch;
  * device tables and buffers for up to max_paths_each paths per structure.
  * Each structure's struct_id is its fourth Philox counter word.  Limits:
  * 1 <= n_ts <= 4096, 1 <= max_paths_each <= 2^30 and n_ts x ceil(max_paths_each
- * / 256) <= 2^30 (one work item per block of 256 paths), else LLL_EINVAL.
- * Synchronous. */
+ * / 256) <= 2^30 (one work item per block of 256 paths), N <= LLL_N_MAX for
+ * every structure, else LLL_EINVAL.  Synchronous. */
 int lll_batch_create(const lll_term_structure *ts, int n_ts, int64_t max_paths_each,
                      lll_batch **batch_out);
 
@@ -339,7 +357,8 @@ int lll_plan_tables(lll_plan *plan, double *x_host, double *w_host, double *kapp
 
 /* Drift b(t_k, T_i) of the live rates at step k for n given rate vectors
  * L_host[n][N], computed by the path kernel's own drift code in the plan's
- * precision; b_host[n][N] (entries of fixed rates are 0). */
+ * precision; b_host[n][N] (entries of fixed rates are 0).  LLL_EUNSUPPORTED
+ * for N > LLL_N_MAX. */
 int lll_plan_drift(lll_plan *plan, int k, const double *L_host, int64_t n, double *b_host,
                    void *stream);
 

@@ -5,9 +5,10 @@ The computation lives in the HIP library ``liblll.so`` behind the C ABI of
 package does not load the library; the first call does, and raises if the
 library is missing.
 """
-from ._lib import (FIRST_ORDER, FP32, FP64, FROZEN, FULL, PICARD, SECOND_ORDER,  # noqa: F401
+from ._lib import (FIRST_ORDER, FP32, FP64, FROZEN, FULL, PICARD, PICARD_MP,  # noqa: F401
+                   SECOND_ORDER,
                    Batch, LLLError, Mlp, Plan, caplet_greeks, load, philox, price_caplets,
                    version)
 
 SCHEMES = {"full": FULL, "picard": PICARD, "frozen": FROZEN, "first_order": FIRST_ORDER,
-           "second_order": SECOND_ORDER}
+           "second_order": SECOND_ORDER, "picard_mp": PICARD_MP}

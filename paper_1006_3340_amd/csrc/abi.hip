@@ -51,7 +51,8 @@ bool finite_all(const double *a, size_t n) {
 int validate(const lll_term_structure *ts) {
     if (!ts) return fail(LLL_EINVAL, "term structure is NULL");
     const int N = ts->n_rates, s = ts->steps_per_period, S = ts->n_strikes;
-    if (N < 1 || N > LLL_N_MAX) return fail(LLL_EINVAL, "n_rates=%d outside 1..%d", N, LLL_N_MAX);
+    if (N < 1 || N > LLL_N_MAX_MP)
+        return fail(LLL_EINVAL, "n_rates=%d outside 1..%d", N, LLL_N_MAX_MP);
     if (s < 1 || s > 100000) return fail(LLL_EINVAL, "steps_per_period=%d must be >= 1", s);
     if ((int64_t)N * s > (int64_t)1 << 24) return fail(LLL_EINVAL, "too many Euler steps");
     if (S < 1 || S > LLL_S_MAX) return fail(LLL_EINVAL, "n_strikes=%d outside 1..%d", S, LLL_S_MAX);
@@ -257,6 +258,7 @@ int lll_plan_destroy(lll_plan *plan) {
         if (plan->ev[i]) (void)hipEventDestroy(plan->ev[i]);
     lll::greeks_free(*plan);
     lll::mlp_plan_free(*plan);
+    lll::picard_mp_free(*plan);
     free_tables(plan->d);
     if (dev != plan->device) (void)hipSetDevice(dev);
     delete plan;
@@ -266,13 +268,25 @@ int lll_plan_destroy(lll_plan *plan) {
 int lll_plan_execute(lll_plan *plan, int scheme, int64_t n_paths, int64_t path_offset,
                      uint64_t seed, double *path_fix_dev, void *stream) {
     if (!plan) return fail(LLL_EINVAL, "plan is NULL");
-    if (scheme < LLL_FULL || scheme > LLL_SECOND_ORDER)
+    if (scheme < LLL_FULL || scheme > LLL_PICARD_MP)
         return fail(LLL_EINVAL, "unknown scheme %d", scheme);
     if (n_paths < 1 || n_paths > plan->max_paths)
         return fail(LLL_EINVAL, "n_paths=%lld outside 1..%lld", (long long)n_paths,
                     (long long)plan->max_paths);
     if (path_offset < 0 || path_offset > ((int64_t)1 << 62))
         return fail(LLL_EINVAL, "path_offset=%lld out of range", (long long)path_offset);
+    const bool mp = scheme == LLL_PICARD_MP;
+    if (!mp && plan->N > LLL_N_MAX)
+        return fail(LLL_EUNSUPPORTED, "N=%d > %d rates runs only as LLL_PICARD_MP", plan->N,
+                    LLL_N_MAX);
+    if (mp && plan->precision != LLL_FP32)
+        return fail(LLL_EUNSUPPORTED, "LLL_PICARD_MP runs on FP32 plans");
+    if (mp && plan->driver != LLL_DRIVER_NIG)
+        return fail(LLL_EUNSUPPORTED, "LLL_PICARD_MP is implemented for the NIG driver");
+    if (mp) {
+        hipError_t ea = lll::picard_mp_alloc(*plan);
+        if (ea != hipSuccess) return fail(LLL_ENOMEM, "PICARD_MP buffers: %s", hipGetErrorString(ea));
+    }
     if (scheme == LLL_FIRST_ORDER && !plan->d.k2) {
         const size_t esz = plan->precision == LLL_FP64 ? sizeof(double) : sizeof(float);
         hipError_t ea = hipMalloc(&plan->d.k2, (size_t)plan->K * plan->nmax * plan->nmax * esz);
@@ -288,8 +302,9 @@ int lll_plan_execute(lll_plan *plan, int scheme, int64_t n_paths, int64_t path_o
     if (e == hipSuccess && scheme == LLL_FIRST_ORDER) e = lll::launch_first_order_tables(*plan, st);
     if (e != hipSuccess) return hip_fail(e, "precompute launch");
     if (t) e = hipEventRecord(plan->ev[1], st);
-    if (e == hipSuccess) e = lll::launch_paths(*plan, scheme, n_paths, path_offset, seed,
-                                              path_fix_dev, st);
+    if (e == hipSuccess)
+        e = mp ? lll::launch_picard_mp(*plan, n_paths, path_offset, seed, path_fix_dev, st)
+               : lll::launch_paths(*plan, scheme, n_paths, path_offset, seed, path_fix_dev, st);
     if (e != hipSuccess) return hip_fail(e, "path kernel launch");
     if (t) e = hipEventRecord(plan->ev[2], st);
     if (e == hipSuccess) e = lll::launch_reduce(*plan, n_paths, st);
@@ -436,6 +451,8 @@ int lll_plan_drift(lll_plan *plan, int k, const double *L_host, int64_t n, doubl
     if (!plan || !L_host || !b_host) return fail(LLL_EINVAL, "NULL argument");
     if (k < 0 || k >= plan->K) return fail(LLL_EINVAL, "step %d outside 0..%d", k, plan->K - 1);
     if (n < 1 || n > ((int64_t)1 << 24)) return fail(LLL_EINVAL, "n=%lld out of range", (long long)n);
+    if (plan->N > LLL_N_MAX)
+        return fail(LLL_EUNSUPPORTED, "the drift kernel handles N <= %d", LLL_N_MAX);
     const int first = k / plan->s;
     for (int64_t i = 0; i < n; ++i)
         for (int r = first; r < plan->N; ++r)
@@ -486,6 +503,8 @@ int lll_batch_create(const lll_term_structure *ts, int n_ts, int64_t max_paths_e
                     (long long)items);
     for (int i = 0; i < n_ts; ++i) {
         int rc = validate(&ts[i]);
+        if (rc == LLL_OK && ts[i].n_rates > LLL_N_MAX)
+            rc = fail(LLL_EINVAL, "n_rates=%d outside 1..%d", ts[i].n_rates, LLL_N_MAX);
         if (rc != LLL_OK) {
             std::string msg = "structure " + std::to_string(i) + ": " + g_last_error;
             return fail(rc, "%s", msg.c_str());
@@ -588,6 +607,8 @@ int lll_plan_greeks(lll_plan *plan, int64_t n_paths, uint64_t seed, void *stream
         return fail(LLL_EUNSUPPORTED, "the adjoint is implemented for the NIG driver");
     if (plan->product != LLL_CAPLETS)
         return fail(LLL_EUNSUPPORTED, "the adjoint differentiates caplets");
+    if (plan->N > LLL_N_MAX)
+        return fail(LLL_EUNSUPPORTED, "the adjoint handles N <= %d", LLL_N_MAX);
     if (n_paths < 1 || n_paths > plan->max_paths)
         return fail(LLL_EINVAL, "n_paths=%lld outside 1..%lld", (long long)n_paths,
                     (long long)plan->max_paths);

@@ -37,6 +37,10 @@ struct DeviceTables {
     void *dt = nullptr;        // [K]
     void *cinv = nullptr;      // [nmax]  1 / (delta L0)
     void *k2 = nullptr;        // [K][nmax][nmax] first-order coefficients (allocated on first use)
+    // maturity-parallel PICARD (FP32, allocated on first use)
+    void *mp_ewq = nullptr;       // [K][N][Q] (E, W E dt)
+    float *mp_ell = nullptr;      // [chunk/4][K][N][4] ell at the predictor
+    float *mp_z = nullptr;        // [chunk/4][N][N][4] per-period state increments
     double *L0s = nullptr, *deltas = nullptr;   // [nmax] FP64 slot layout
     // reduction
     double *partials = nullptr;  // [max_waves][N][NSTAT]
@@ -68,6 +72,7 @@ struct lll_plan {
     int product = 0;  // lll_product
     double B0_T1 = 0, alpha = 0, beta = 0, delta_nig = 0, c = 0;
     int64_t max_paths = 0, max_waves = 0, max_chunks = 0;
+    int64_t mp_chunk = 0;  // paths per chunk of the maturity-parallel PICARD
     int device = 0;
     std::vector<double> tenor, delta, L0, vol, strikes;
     lll::DeviceTables d;
@@ -119,6 +124,15 @@ hipError_t launch_batched(const lll_batch &b, int scheme, hipStream_t st);
 
 // precompute.hip
 hipError_t launch_precompute(const lll_plan &p, hipStream_t st);
+
+// picard_mp.hip: PICARD in the maturity-parallel layout; its buffers hold at
+// most kMpBufferBytes, so larger runs go in chunks of picard_mp_chunk paths
+constexpr int64_t kMpBufferBytes = int64_t(2) << 30;
+int64_t picard_mp_chunk(const lll_plan &p);
+hipError_t picard_mp_alloc(lll_plan &p);
+void picard_mp_free(lll_plan &p);
+hipError_t launch_picard_mp(const lll_plan &p, int64_t n_paths, int64_t path_offset,
+                            uint64_t seed, double *path_fix, hipStream_t st);
 
 // paths.hip
 hipError_t launch_paths(const lll_plan &p, int scheme, int64_t n_paths, int64_t path_offset,

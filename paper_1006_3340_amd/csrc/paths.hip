@@ -121,7 +121,8 @@ int bucket_for(int n_rates) {
     if (n_rates <= 16) return 16;
     if (n_rates <= 24) return 24;
     if (n_rates <= 32) return 32;
-    return 40;
+    if (n_rates <= 40) return 40;
+    return 64;  // tables only: the maturity-parallel PICARD
 }
 
 hipError_t launch_paths(const lll_plan &p, int scheme, int64_t n_paths, int64_t path_offset,

@@ -125,8 +125,8 @@ __global__ void __launch_bounds__(64) setup_tables_kernel(
     double *__restrict__ kappa_out, double *__restrict__ E_out, double *__restrict__ b0_out,
     Real *__restrict__ ew, Real *__restrict__ lam_t, Real *__restrict__ drift0,
     Real *__restrict__ frozen, Real *__restrict__ dt_t) {
-    __shared__ double cq[40][kQ];    // WE_q R_q contributions per rate
-    __shared__ double kap[40];
+    __shared__ double cq[LLL_N_MAX_MP][kQ];    // WE_q R_q contributions per rate
+    __shared__ double kap[LLL_N_MAX_MP];
     const int k = blockIdx.x;
     const int q = threadIdx.x;
     const int m = k / s;

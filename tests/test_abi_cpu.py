@@ -70,8 +70,8 @@ def test_validation_errors():
     _expect(EMOMENT, k.copy(vol=k.vol * 1.05))
     # FP64 path kernel only up to 24 rates
     _expect(EUNSUP, workloads.learned_drift(), precision=1)
-    big = workloads.make_structure(41, 0.25, 0.03, 2, lambda t, T, r: 0.1, [1.0])
-    _expect(EINVAL, big)
+    big = workloads.make_structure(65, 0.25, 0.03, 2, lambda t, T, r: 0.1, [1.0])
+    _expect(EINVAL, big)                                  # beyond LLL_N_MAX_MP
     bad = ts.copy()
     bad.product = 2                                       # neither caplets nor swaptions
     _expect(EINVAL, bad)
@@ -97,3 +97,8 @@ def test_batch_validation_errors():
     with pytest.raises(lll.LLLError) as ei:
         lll.Batch([ts.copy(L0=-ts.L0)], max_paths_each=64)
     assert ei.value.code == -1
+    # batches run the 40-slot path kernel: N = 41 is rejected before allocation
+    big = workloads.make_structure(41, 0.25, 0.03, 2, lambda t, T, r: 0.1, [1.0])
+    with pytest.raises(lll.LLLError) as ei:
+        lll.Batch([ts, big], max_paths_each=64)
+    assert ei.value.code == -1 and "structure 1" in str(ei.value)

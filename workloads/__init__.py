@@ -35,7 +35,8 @@ SCHEME_MLP = 3
 SCHEME_NAMES = {"full": SCHEME_FULL, "picard": SCHEME_PICARD,
                 "frozen": SCHEME_FROZEN, "mlp": SCHEME_MLP}
 
-N_MAX = 40
+N_MAX = 40       # path-per-lane kernels
+N_MAX_MP = 64    # the maturity-parallel PICARD layout
 
 
 @dataclasses.dataclass
@@ -173,6 +174,15 @@ def learned_drift() -> TermStructure:
                           name="mlp_n40")
 
 
+def maturity_parallel() -> TermStructure:
+    """Few paths, many rates: N=60 quarterly (15y), L0_i = 0.03 + 0.0005 i, the
+    exp-decay vol, NIG(18,-4,1), 10 steps per period, strikes {0.8, 1.0, 1.2} x
+    forward; priced with 10^4 paths."""
+    L0 = 0.03 + 0.0005 * np.arange(1, 61)
+    return make_structure(60, 0.25, L0, 10, exp_decay_vol(), [0.8, 1.0, 1.2],
+                          name="mp_n60")
+
+
 def adjoint_greeks(levels: Optional[np.ndarray] = None,
                    L0: Optional[np.ndarray] = None) -> TermStructure:
     """N=40 quarterly, ATM caplets; vol lambda = v_i + 0.1 e^{-0.5(T_i - t)} with
@@ -263,4 +273,5 @@ WORKLOADS = {
     "mlp_n40": learned_drift,
     "adjoint_n40": adjoint_greeks,
     "kluge_n9": kluge_example,
+    "mp_n60": maturity_parallel,
 }
