@@ -39,8 +39,10 @@ struct DeviceTables {
     void *k2 = nullptr;        // [K][nmax][nmax] first-order coefficients (allocated on first use)
     // maturity-parallel PICARD (FP32, allocated on first use)
     void *mp_ewq = nullptr;       // [K][N][Q] (E, W E dt)
-    float *mp_ell = nullptr;      // [chunk/4][K][N][4] ell at the predictor
+    float *mp_ell = nullptr;      // [chunk/4][s N (N+1)/2][4] ell at the predictor, live rates
     float *mp_z = nullptr;        // [chunk/4][N][N][4] per-period state increments
+    double *mp_pay = nullptr;     // [N][S+1][chunk] per-path payoff values
+    float *mp_dh = nullptr;       // [chunk/4][K][4] driver increments
     double *L0s = nullptr, *deltas = nullptr;   // [nmax] FP64 slot layout
     // reduction
     double *partials = nullptr;  // [max_waves][N][NSTAT]

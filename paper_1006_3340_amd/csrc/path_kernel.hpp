@@ -203,6 +203,13 @@ __device__ __forceinline__ void step(const PathArgs<Real> &a, int k, Real dH, Re
     }
 }
 
+// Payoff before the positive part of strike K at the fixing of rate r:
+// swaption (Q - 1) - K A, caplet D (L_r - K) (quantities as in fixing_sums).
+__device__ __forceinline__ double payoff_value(bool swaption, double K, double Q, double A,
+                                              double D, double Lc) {
+    return swaption ? (Q - 1.0) - K * A : D * (Lc - K);
+}
+
 // Wavefront sums (FP64) of the payoffs of the fixing of rate r, given
 // Q = prod_{l>=r}(1 + delta_l L_l), A = sum_{l>=r} delta_l prod_{j>l}(1 + delta_j L_j),
 // D = prod_{l>r}(1 + delta_l L_l) and L_r: per strike the sum, the sum of
@@ -220,7 +227,7 @@ __device__ __forceinline__ void fixing_sums(const PathArgs<Real> &a, int r, int6
     const bool lane0 = (threadIdx.x % kWave) == 0;
     for (int t = 0; t < S; ++t) {
         const double K = a.strikes[r * S + t];
-        const double v = swaption ? (Q - 1.0) - K * A : D * (Lc - K);
+        const double v = payoff_value(swaption, K, Q, A, D, Lc);
         const double pay = active ? fmax(v, 0.0) : 0.0;
         const double s1 = wave_sum(pay);
         const double s2 = wave_sum(pay * pay);
@@ -320,18 +327,20 @@ __device__ __forceinline__ void payoff(const PathArgs<Real> &a, int m, int64_t g
 }
 
 // Payoffs of the LDS-state kernels: the state is read from the thread's LDS
-// column slot by slot in a loop, so no register copy of all slots (whose
-// unrolled FP64 products would otherwise set the kernel's register count:
-// 86 -> 58 VGPRs for FULL at 24 slots).  Same quantities as payoff().
-template <typename Real, int NMAX, int PRODUCT>
-__device__ __forceinline__ void payoff_lds(const PathArgs<Real> &a, int m, int64_t gid,
-                                           bool active, const Real *xs, int j0) {
-    const int r = m;
-    const bool swaption =
-        PRODUCT == kAnyProduct ? a.product == LLL_SWAPTIONS : PRODUCT == LLL_SWAPTIONS;
-    double Q = 1.0, A = 0.0, D = 1.0, Lc = 0.0;
+// column (slot stride STRIDE) slot by slot in a loop, so no register copy of
+// all slots (whose unrolled FP64 products would otherwise set the kernel's
+// register count: 86 -> 58 VGPRs for FULL at 24 slots).  Same quantities as
+// payoff(): Q, A, D and L_r of fixing_sums.
+template <typename Real, int NMAX, int STRIDE = kBlock>
+__device__ __forceinline__ void fixing_quantities_lds(const PathArgs<Real> &a, const Real *xs,
+                                                      int j0, double &Q, double &A, double &D,
+                                                      double &Lc) {
+    Q = 1.0;
+    A = 0.0;
+    D = 1.0;
+    Lc = 0.0;
     for (int j = NMAX - 1; j >= j0; --j) {
-        const double L = a.L0s[j] * static_cast<double>(exp(xs[j * kBlock]));
+        const double L = a.L0s[j] * static_cast<double>(exp(xs[j * STRIDE]));
         if (j == j0) {
             D = Q;
             Lc = L;
@@ -339,7 +348,16 @@ __device__ __forceinline__ void payoff_lds(const PathArgs<Real> &a, int m, int64
         A = fma(a.deltas[j], Q, A);
         Q *= 1.0 + a.deltas[j] * L;
     }
-    fixing_sums(a, r, gid, active, swaption, Q, A, D, Lc);
+}
+
+template <typename Real, int NMAX, int PRODUCT>
+__device__ __forceinline__ void payoff_lds(const PathArgs<Real> &a, int m, int64_t gid,
+                                           bool active, const Real *xs, int j0) {
+    const bool swaption =
+        PRODUCT == kAnyProduct ? a.product == LLL_SWAPTIONS : PRODUCT == LLL_SWAPTIONS;
+    double Q, A, D, Lc;
+    fixing_quantities_lds<Real, NMAX>(a, xs, j0, Q, A, D, Lc);
+    fixing_sums(a, m, gid, active, swaption, Q, A, D, Lc);
 }
 
 // The same step with the state X held in LDS (column `xs`, stride kBlock) for
