@@ -32,7 +32,7 @@ PEAK_FP32 = 157.3e12   # MI355X vector FP32, FLOP/s
 # WRITE_SIZE runs of this benchmark, each scaled by the same counter's reading
 # for a 1 GiB device copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0), keyed by the
 # hash of the kernel sources they were taken on; any other hash reports null.
-TRAFFIC_BYTES = {"40f42f7dbf2bf636": {"full": 252383948, "picard": 222761574}}
+TRAFFIC_BYTES = {"34bbcd17e37e1bd7": {"full": 237057581, "picard": 233805984}}
 KERNEL_SOURCES = ["paper_1006_3340_amd/csrc/path_kernel.hpp",
                   "paper_1006_3340_amd/csrc/lll_device.hpp",
                   "paper_1006_3340_amd/_build.py"]
@@ -268,6 +268,42 @@ def bench_swaptions(lll, stream, n: int = 1 << 20) -> dict:
     return out
 
 
+def bench_maturity_parallel(lll, stream) -> dict:
+    """Few paths, many rates: PICARD in the maturity-parallel layout (PICARD_MP)
+    against the one-path-per-lane FULL and PICARD kernels at 10^4 paths (N = 20,
+    40; N = 60 runs only as PICARD_MP), and at 2^17 paths where the path kernel
+    fills the GPU.  Times are the library's HIP events around all of the
+    scheme's kernels (PICARD_MP: increments, predictor, period items, payoffs);
+    TFLOP/s counts PICARD's algorithmic flops.  Differences are max relative
+    caplet differences over the non-zero prices, on the same random streams."""
+    out = {}
+    for wl, n in (("mp_n60", 10000), ("mlp_n40", 10000), ("gpu_n20", 10000), ("mlp_n40", 1 << 17)):
+        ts = workloads.WORKLOADS[wl]()
+        names = ["picard_mp"] + ([] if ts.n_rates > lll.N_MAX else ["full", "picard"])
+        res, prices = {}, {}
+        with lll.Plan(ts, precision=lll.FP32, max_paths=n) as plan:
+            plan.set_timing(True)
+            for name in names:
+                plan.execute(lll.SCHEMES[name], n, seed=1, stream=stream)   # warmup
+                ms = []
+                for _ in range(3):
+                    plan.execute(lll.SCHEMES[name], n, seed=1, stream=stream)
+                    ms.append(plan.timing()["paths"])
+                t = float(np.median(ms)) / 1e3
+                prices[name] = plan.results(stream)["price"]
+                fl = flops_per_path(ts, "picard" if name == "picard_mp" else name) * n
+                res[name] = {"ms": t * 1e3, "path_steps_per_s": n * ts.n_steps / t,
+                             "fp32_tflops": fl / t / 1e12, "frac_fp32_peak": fl / t / PEAK_FP32}
+        for ref in ("picard", "full"):
+            if ref in prices:
+                live = prices[ref] > 0.0
+                res["picard_mp"][f"max_rel_diff_vs_{ref}"] = float(
+                    np.max(np.abs(prices["picard_mp"][live] / prices[ref][live] - 1)))
+                res["picard_mp"][f"speedup_vs_{ref}"] = res[ref]["ms"] / res["picard_mp"]["ms"]
+        out[f"{wl}_{n}"] = res
+    return out
+
+
 def bench_batched(lll, stream, schemes, n_each: int = 1 << 18, reps: int = 2) -> dict:
     """64 independent structures in one persistent launch: kernel time (HIP events
     recorded by the library), path-steps/s and FP32 fraction of peak."""
@@ -304,6 +340,8 @@ def main(argv=None) -> int:
                     help="also time the pathwise Greeks pass (N=40, 2^20 paths)")
     ap.add_argument("--mlp", type=int, default=1,
                     help="also train the drift surrogate and time it (N=40, 2^20 paths)")
+    ap.add_argument("--mp", type=int, default=1,
+                    help="also time the maturity-parallel PICARD layout (1) or not (0)")
     ap.add_argument("--kluge", type=int, default=1,
                     help="also reproduce the paper's example (implied-volatility errors, FP64)")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -408,6 +446,8 @@ def main(argv=None) -> int:
         out["adjoint"] = bench_adjoint(lll, stream)
     if args.mlp:
         out["mlp"] = bench_mlp(lll, stream)
+    if args.mp:
+        out["maturity_parallel"] = bench_maturity_parallel(lll, stream)
     if args.kluge:
         out["kluge"] = bench_kluge(lll, stream)
     if args.cpu_sample > 0:

@@ -5,8 +5,8 @@ The computation lives in the HIP library ``liblll.so`` behind the C ABI of
 package does not load the library; the first call does, and raises if the
 library is missing.
 """
-from ._lib import (FIRST_ORDER, FP32, FP64, FROZEN, FULL, PICARD, PICARD_MP,  # noqa: F401
-                   SECOND_ORDER,
+from ._lib import (FIRST_ORDER, FP32, FP64, FROZEN, FULL, N_MAX, N_MAX_MP,  # noqa: F401
+                   PICARD, PICARD_MP, SECOND_ORDER,
                    Batch, LLLError, Mlp, Plan, caplet_greeks, load, philox, price_caplets,
                    version)
 

@@ -86,7 +86,7 @@ def test_mp_full_size(gpu_lib, oracle_mod):
 
 
 def test_mp_chunks_deterministic_and_split_range(gpu_lib):
-    """2^15 paths at N = 60 run in three chunks of the 2 GiB buffers: the wave
+    """2^15 paths at N = 60 run in two chunks of the 2 GiB buffers: the wave
     partials are bitwise those of two half-range calls and of a repeat."""
     ts = workloads.maturity_parallel()
     n = 1 << 15
