@@ -109,8 +109,22 @@ def adjoint_flops_per_path(ts) -> int:
     return total
 
 
+def vjp_flops_per_path(ts) -> int:
+    """Algorithmic FP32 flops of the vector-Jacobian product per path: the FULL
+    forward pass, then for every period m (n = N - m rates carried) and each of
+    its steps one recomputed FULL step plus the reverse step."""
+    N, s = ts.n_rates, ts.steps_per_period
+    total = flops_per_path(ts, "full")
+    for m in range(N):
+        n = N - m
+        total += s * (flops_per_path_step("full", n) + 18 * Q * n + 10 * n)
+    return total
+
+
 def bench_adjoint(lll, stream, n: int = 1 << 20) -> dict:
-    """Pathwise Greeks of 40 ATM caplets (N=40 quarterly, 2^20 paths, FP32)."""
+    """Pathwise Greeks of 40 ATM caplets (N=40 quarterly, 2^20 paths, FP32): the
+    full Jacobian (one reverse sweep per caplet) and the vector-Jacobian product
+    with unit weights (one sweep; what the autograd backward runs)."""
     ts = workloads.adjoint_greeks()
     with lll.Plan(ts, precision=lll.FP32, max_paths=n) as plan:
         plan.set_timing(True)
@@ -118,13 +132,25 @@ def bench_adjoint(lll, stream, n: int = 1 << 20) -> dict:
         plan.greeks(n, seed=1, stream=stream)
         ms = plan.timing()["paths"]
         g = plan.greeks_results(stream)
+        w = np.ones(ts.n_rates)
+        plan.greeks_vjp(n, w, seed=1, stream=stream)   # warmup
+        plan.greeks_vjp(n, w, seed=1, stream=stream)
+        ms_vjp = plan.timing()["paths"]
+        r = plan.greeks_vjp_results(stream)
     if not np.all(np.isfinite(g["dP_dL0"])):
         raise RuntimeError("non-finite Greeks")
     fl = adjoint_flops_per_path(ts) * n
     t = ms / 1e3
+    fv = vjp_flops_per_path(ts) * n
+    tv = ms_vjp / 1e3
+    ref = w @ g["dP_dL0"]
     return {"workload": ts.name, "n_paths": n, "ms": ms,
             "forward_path_steps_per_s": n * ts.n_steps / t,
-            "fp32_tflops": fl / t / 1e12, "frac_fp32_peak": fl / t / PEAK_FP32}
+            "fp32_tflops": fl / t / 1e12, "frac_fp32_peak": fl / t / PEAK_FP32,
+            "vjp": {"ms": ms_vjp, "fp32_tflops": fv / tv / 1e12, "frac_fp32_peak": fv / tv / PEAK_FP32,
+                    "speedup_vs_jacobian": ms / ms_vjp,
+                    "max_rel_diff_vs_jacobian": float(np.max(np.abs(r["vjp_L0"] - ref)) /
+                                                      np.max(np.abs(ref)))}}
 
 
 PEAK_BF16 = 2.5e15     # MI355X dense BF16 matrix cores, FLOP/s

@@ -207,6 +207,26 @@ int lll_price_caplets(const lll_term_structure *ts, int64_t n_paths, int scheme,
  * N > LLL_N_MAX.  Asynchronous. */
 int lll_plan_greeks(lll_plan *plan, int64_t n_paths, uint64_t seed, void *stream);
 
+/* Vector-Jacobian product of the same caplet prices (strike 0) with weights
+ * g = weights_host[N] (host, read before return): out_L0[l] = sum_i g_i
+ * dP_i/dL(0,T_l) and out_vol[l] = sum_i g_i dP_i/dv_l, the quantities that
+ * reverse-mode differentiation of a scalar function of the prices needs.  One
+ * reverse sweep, from the last fixing date to t = 0, whose state adjoint is
+ * seeded with g_i times the payoff adjoint of caplet i at its fixing date
+ * (paper Section 3.3, eq. (caplet)); per accrual period one kernel recomputes
+ * the period from its tenor-date checkpoint and walks it back.  Cost: the
+ * forward pass plus one recompute and one reverse pass, against one sweep per
+ * caplet for the full Jacobian of lll_plan_greeks (same conventions, buffers
+ * and restrictions; equal to g^T J up to FP32 summation order).
+ * LLL_EINVAL for NULL or non-finite weights.  Asynchronous. */
+int lll_plan_greeks_vjp(lll_plan *plan, int64_t n_paths, uint64_t seed, const double *weights_host,
+                        void *stream);
+
+/* Results of the last lll_plan_greeks_vjp: price_host[N] (strike 0),
+ * vjp_L0_host[N], vjp_vol_host[N]; waits for `stream`.  Any pointer may be NULL. */
+int lll_plan_greeks_vjp_results(lll_plan *plan, double *price_host, double *vjp_L0_host,
+                                double *vjp_vol_host, void *stream);
+
 /* Wait for `stream` and copy the last Greeks pass: price_host[N] (strike 0),
  * dP_dL0_host[N][N] and dP_dvol_host[N][N], row = caplet, column = input rate.
  * Any pointer may be NULL. */

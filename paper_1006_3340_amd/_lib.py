@@ -29,7 +29,8 @@ EXPORTS = ["lll_version", "lll_last_error", "lll_plan_create", "lll_plan_execute
            "lll_price_caplets", "lll_philox", "lll_plan_increments", "lll_plan_tables",
            "lll_plan_drift", "lll_plan_set_timing", "lll_plan_timing", "lll_batch_create",
            "lll_batch_execute", "lll_batch_results", "lll_batch_set_timing", "lll_batch_timing",
-           "lll_batch_destroy", "lll_plan_greeks", "lll_plan_greeks_results", "lll_caplet_greeks",
+           "lll_batch_destroy", "lll_plan_greeks", "lll_plan_greeks_results", "lll_plan_greeks_vjp",
+           "lll_plan_greeks_vjp_results", "lll_caplet_greeks",
            "lll_mlp_create", "lll_mlp_destroy", "lll_mlp_params", "lll_mlp_generate",
            "lll_mlp_info", "lll_mlp_set_box", "lll_mlp_pairs", "lll_mlp_train", "lll_mlp_eval",
            "lll_plan_execute_mlp", "lll_plan_mlp_stats"]
@@ -107,6 +108,8 @@ def load():
     lib.lll_plan_mlp_stats.argtypes = [vp, dp, vp]
     lib.lll_plan_greeks.argtypes = [vp, i64, u64, vp]
     lib.lll_plan_greeks_results.argtypes = [vp, dp, dp, dp, vp]
+    lib.lll_plan_greeks_vjp.argtypes = [vp, i64, u64, dp, vp]
+    lib.lll_plan_greeks_vjp_results.argtypes = [vp, dp, dp, dp, vp]
     lib.lll_caplet_greeks.argtypes = [ctypes.POINTER(TermStructureC), i64, u64, dp, dp, dp, vp]
     lib.lll_batch_create.argtypes = [ctypes.POINTER(TermStructureC), i32, i64, ctypes.POINTER(vp)]
     lib.lll_batch_execute.argtypes = [vp, i32, i64, u64, vp]
@@ -237,6 +240,20 @@ class Plan:
         """Enqueue the FULL pricing pass with the pathwise adjoint (lll_plan_greeks)."""
         _check(self.lib.lll_plan_greeks(self.h, int(n_paths), int(seed), stream_handle(stream)))
         self.n_paths = int(n_paths)
+
+    def greeks_vjp(self, n_paths: int, weights, seed: int = 1, stream=None):
+        """Enqueue the single-sweep vector-Jacobian product (lll_plan_greeks_vjp)."""
+        w = np.ascontiguousarray(np.asarray(weights, dtype=np.float64).reshape(self.N))
+        _check(self.lib.lll_plan_greeks_vjp(self.h, int(n_paths), int(seed), _dp(w),
+                                            stream_handle(stream)))
+        self.n_paths = int(n_paths)
+
+    def greeks_vjp_results(self, stream=None) -> dict:
+        N = self.N
+        price = np.zeros(N); gL = np.zeros(N); gV = np.zeros(N)
+        _check(self.lib.lll_plan_greeks_vjp_results(self.h, _dp(price), _dp(gL), _dp(gV),
+                                                    stream_handle(stream)))
+        return {"price": price, "vjp_L0": gL, "vjp_vol": gV}
 
     def greeks_results(self, stream=None) -> dict:
         N = self.N

@@ -4,9 +4,10 @@
 prices (strike 0 of each caplet) of the term structure ``ts`` with its initial
 forwards replaced by ``L0`` and its vol curves shifted so that
 lambda(t, T_i) = vol_levels[i] + (ts.vol[k, i] - base_levels[i]) (a parallel
-shift of each rate's curve).  The backward pass returns grad_out @ J with the
-Jacobians computed on the GPU by ``lll_plan_greeks``; the forward pass and the
-Jacobians come from the same launch.
+shift of each rate's curve).  The forward pass is a FULL pricing pass; the
+backward pass is the GPU's vector-Jacobian product ``lll_plan_greeks_vjp``
+with the incoming gradient as the weights (one reverse sweep, on the forward
+pass's random streams), not the full Jacobian.
 """
 from __future__ import annotations
 
@@ -33,15 +34,18 @@ class CapletPrice(torch.autograd.Function):
         base = np.zeros(ts.n_rates) if base_levels is None else np.asarray(base_levels, float)
         ts2 = shifted(ts, L0.detach().cpu().double().numpy(), levels.detach().cpu().double().numpy(),
                       base)
-        g = _lib.caplet_greeks(ts2, n_paths, seed)
-        ctx.save_for_backward(torch.from_numpy(g["dP_dL0"]), torch.from_numpy(g["dP_dvol"]))
-        ctx.dev = L0.device
-        return torch.from_numpy(g["price"]).to(L0.device, L0.dtype)
+        plan = _lib.Plan(ts2, precision=_lib.FP32, max_paths=n_paths)
+        plan.execute(_lib.FULL, n_paths, seed=seed)
+        price = plan.results()["price"][:, 0].copy()
+        ctx.plan, ctx.n_paths, ctx.seed, ctx.dev = plan, n_paths, seed, L0.device
+        return torch.from_numpy(price).to(L0.device, L0.dtype)
 
     @staticmethod
     def backward(ctx, grad_out):
-        JL, JV = ctx.saved_tensors
-        go = grad_out.detach().cpu().double()
-        gL = (go @ JL).to(ctx.dev, grad_out.dtype)
-        gV = (go @ JV).to(ctx.dev, grad_out.dtype)
+        plan = ctx.plan
+        plan.greeks_vjp(ctx.n_paths, grad_out.detach().cpu().double().numpy(), seed=ctx.seed)
+        r = plan.greeks_vjp_results()
+        plan.close()
+        gL = torch.from_numpy(r["vjp_L0"]).to(ctx.dev, grad_out.dtype)
+        gV = torch.from_numpy(r["vjp_vol"]).to(ctx.dev, grad_out.dtype)
         return gL, gV, None, None, None, None

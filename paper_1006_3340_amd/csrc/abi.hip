@@ -599,7 +599,8 @@ int lll_batch_results(lll_batch *batch, int index, double *price_host, double *s
                             mart_se_host, n_itm_host, stream);
 }
 
-int lll_plan_greeks(lll_plan *plan, int64_t n_paths, uint64_t seed, void *stream) {
+// Checks shared by the Greeks entry points; allocates the adjoint buffers.
+static int greeks_prepare(lll_plan *plan, int64_t n_paths) {
     if (!plan) return fail(LLL_EINVAL, "plan is NULL");
     if (plan->precision != LLL_FP32)
         return fail(LLL_EUNSUPPORTED, "the adjoint runs on FP32 plans");
@@ -618,6 +619,13 @@ int lll_plan_greeks(lll_plan *plan, int64_t n_paths, uint64_t seed, void *stream
         return fail(e == hipErrorOutOfMemory ? LLL_ENOMEM : LLL_EHIP,
                     "allocating adjoint checkpoints: %s", hipGetErrorString(e));
     }
+    return LLL_OK;
+}
+
+int lll_plan_greeks(lll_plan *plan, int64_t n_paths, uint64_t seed, void *stream) {
+    const int rc = greeks_prepare(plan, n_paths);
+    if (rc != LLL_OK) return rc;
+    hipError_t e = hipSuccess;
     hipStream_t st = as_stream(stream);
     const bool t = plan->timing;
     // the whole Greeks pass is timed as the path stage (events 1 -> 2)
@@ -654,6 +662,50 @@ int lll_plan_greeks_results(lll_plan *plan, double *price_host, double *dP_dL0_h
     if (price_host) std::memcpy(price_host, out.data() + 2 * N * N, N * sizeof(double));
     if (!finite_all(out.data(), out.size()))
         return fail(LLL_ENUMERIC, "non-finite Greeks");
+    return LLL_OK;
+}
+
+int lll_plan_greeks_vjp(lll_plan *plan, int64_t n_paths, uint64_t seed, const double *weights_host,
+                        void *stream) {
+    if (!weights_host) return fail(LLL_EINVAL, "weights are NULL");
+    const int rc = greeks_prepare(plan, n_paths);
+    if (rc != LLL_OK) return rc;
+    if (!finite_all(weights_host, plan->N)) return fail(LLL_EINVAL, "non-finite weight");
+    hipStream_t st = as_stream(stream);
+    const bool t = plan->timing;
+    hipError_t e = hipSuccess;
+    if (t) e = hipEventRecord(plan->ev[0], st);
+    if (t && e == hipSuccess) e = hipEventRecord(plan->ev[1], st);
+    if (e == hipSuccess) e = lll::launch_greeks_vjp(*plan, n_paths, seed, weights_host, st);
+    if (e != hipSuccess) return hip_fail(e, "adjoint launch");
+    if (t) {
+        e = hipEventRecord(plan->ev[2], st);
+        if (e == hipSuccess) e = hipEventRecord(plan->ev[3], st);
+        if (e != hipSuccess) return hip_fail(e, "recording timing events");
+    }
+    plan->timed = t;
+    plan->last_n_paths = n_paths;
+    plan->executed = true;
+    plan->vjp_done = true;
+    return LLL_OK;
+}
+
+int lll_plan_greeks_vjp_results(lll_plan *plan, double *price_host, double *vjp_L0_host,
+                                double *vjp_vol_host, void *stream) {
+    if (!plan) return fail(LLL_EINVAL, "plan is NULL");
+    if (!plan->vjp_done) return fail(LLL_EINVAL, "no vector-Jacobian pass has run on this plan");
+    const size_t N = plan->N;
+    std::vector<double> out(3 * N);
+    hipStream_t st = as_stream(stream);
+    hipError_t e = hipMemcpyAsync(out.data(), plan->g.vjp_out, out.size() * sizeof(double),
+                                  hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "reading the vector-Jacobian product");
+    if (price_host) std::memcpy(price_host, out.data(), N * sizeof(double));
+    if (vjp_L0_host) std::memcpy(vjp_L0_host, out.data() + N, N * sizeof(double));
+    if (vjp_vol_host) std::memcpy(vjp_vol_host, out.data() + 2 * N, N * sizeof(double));
+    if (!finite_all(out.data(), out.size()))
+        return fail(LLL_ENUMERIC, "non-finite vector-Jacobian product");
     return LLL_OK;
 }
 

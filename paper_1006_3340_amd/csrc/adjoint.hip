@@ -13,6 +13,15 @@ extern template hipError_t launch_adjoint_bucket<16>(const PathArgs<float> &, co
 extern template hipError_t launch_adjoint_bucket<24>(const PathArgs<float> &, const AdjArgs &, hipStream_t);
 extern template hipError_t launch_adjoint_bucket<32>(const PathArgs<float> &, const AdjArgs &, hipStream_t);
 extern template hipError_t launch_adjoint_bucket<40>(const PathArgs<float> &, const AdjArgs &, hipStream_t);
+#define LLL_VJP_EXTERN(NM)                                                                         \
+    extern template hipError_t launch_vjp_bucket<NM>(const PathArgs<float> &, const AdjArgs &,    \
+                                                     const VjpArgs &, const float *, hipStream_t);
+LLL_VJP_EXTERN(8)
+LLL_VJP_EXTERN(16)
+LLL_VJP_EXTERN(24)
+LLL_VJP_EXTERN(32)
+LLL_VJP_EXTERN(40)
+#undef LLL_VJP_EXTERN
 
 namespace {
 
@@ -76,6 +85,35 @@ __global__ void __launch_bounds__(64) greeks_finalize_kernel(
     }
 }
 
+// The vector-Jacobian product from the swept sums (seeds g_i delta_i):
+// sum_i g_i dP_i/dL0_l = B(0,T_*) mean(L0bar_l) - (sum_i g_i P_i) delta_l / (1 + delta_l L0_l),
+// sum_i g_i dP_i/dvol_l = B(0,T_*) mean(vbar_l); out = [price (strike 0), dL0, dvol].
+struct VjpWeights {
+    double g[LLL_N_MAX];
+};
+
+__global__ void __launch_bounds__(64) vjp_finalize_kernel(
+    const double *__restrict__ vsums, const double *__restrict__ results,
+    const double *__restrict__ delta, const double *__restrict__ L0, VjpWeights wts, int N, int S,
+    double B0_T1, int64_t n_paths, double *__restrict__ out) {
+    double prod_all = 1.0, gP = 0.0;
+    for (int l = 0; l < N; ++l) {
+        prod_all *= 1.0 + delta[l] * L0[l];
+        gP += wts.g[l] * results[l * S];
+    }
+    const double scale = B0_T1 / prod_all / static_cast<double>(n_paths);
+    for (int l = threadIdx.x; l < N; l += blockDim.x) {
+        out[l] = results[l * S];
+        out[N + l] = scale * vsums[l] - gP * delta[l] / (1.0 + delta[l] * L0[l]);
+        out[2 * N + l] = scale * vsums[N + l];
+    }
+}
+
+__global__ void __launch_bounds__(256) zero_kernel(double *__restrict__ a, int64_t n) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (i < n) a[i] = 0.0;
+}
+
 __global__ void __launch_bounds__(256) reduce_cols_kernel(const double *__restrict__ in,
                                                           int64_t rows, int cols,
                                                           int64_t rows_per_chunk,
@@ -112,19 +150,25 @@ hipError_t greeks_alloc(lll_plan &p) {
     A((void **)&g.gchunks, (size_t)p.max_chunks * N * 2 * N * sizeof(double));
     A((void **)&g.gsums, N * 2 * N * sizeof(double));
     A((void **)&g.out, (2 * N * N + N) * sizeof(double));
+    A((void **)&g.vjp_xb, N * P * sizeof(float));
+    A((void **)&g.vjp_out, 3 * N * sizeof(double));
     return e;
 }
 
 void greeks_free(lll_plan &p) {
     GreeksBuffers &g = p.g;
     void *ptrs[] = {g.xe, g.dkap, g.w32, g.inv_L0, g.ckpt, g.fix, g.scr, g.scr_dh, g.gpart,
-                    g.gchunks, g.gsums, g.out};
+                    g.gchunks, g.gsums, g.out, g.vjp_xb, g.vjp_out};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     p.g = GreeksBuffers{};
 }
 
-hipError_t launch_greeks(const lll_plan &p, int64_t n_paths, uint64_t seed, hipStream_t st) {
+namespace {
+
+// Precompute, the adjoint tables and the kernel arguments of a Greeks pass.
+hipError_t adjoint_setup(const lll_plan &p, int64_t n_paths, uint64_t seed, hipStream_t st,
+                         adj::AdjArgs &g) {
     using namespace adj;
     const DeviceTables &d = p.d;
     const GreeksBuffers &gb = p.g;
@@ -134,9 +178,6 @@ hipError_t launch_greeks(const lll_plan &p, int64_t n_paths, uint64_t seed, hipS
                        d.vol, d.x, d.w, p.N, p.s, p.off, p.nmax, p.alpha, p.beta, p.delta_nig,
                        gb.xe, gb.dkap, gb.w32, gb.inv_L0);
     e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    PathArgs<float> a = detail::make_args<float>(p, seed, n_paths, 0, nullptr);
-    AdjArgs g;
     g.xe = detail::as_const<float>(gb.xe);
     g.dkap = detail::as_const<float>(gb.dkap);
     g.w = detail::as_const<float>(gb.w32);
@@ -147,6 +188,74 @@ hipError_t launch_greeks(const lll_plan &p, int64_t n_paths, uint64_t seed, hipS
     g.scr_dh = gb.scr_dh;
     g.gpart = gb.gpart;
     g.n_paths = n_paths;
+    return e;
+}
+
+// Fixed-order column sums of rows x cols per-wave partials into `out` (via the
+// chunk buffer).
+hipError_t reduce_cols(const double *in, int64_t rows, int cols, double *chunks_buf, double *out,
+                       hipStream_t st) {
+    const int64_t chunks = (rows + 255) / 256;
+    hipLaunchKernelGGL(adj::reduce_cols_kernel, dim3(static_cast<unsigned>(chunks)), dim3(256), 0,
+                       st, in, rows, cols, 256, chunks_buf);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(adj::reduce_cols_kernel, dim3(1), dim3(256), 0, st, chunks_buf, chunks, cols,
+                       chunks, out);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_greeks_vjp(const lll_plan &p, int64_t n_paths, uint64_t seed,
+                             const double *weights, hipStream_t st) {
+    using namespace adj;
+    const GreeksBuffers &gb = p.g;
+    AdjArgs g;
+    hipError_t e = adjoint_setup(p, n_paths, seed, st, g);
+    if (e != hipSuccess) return e;
+    PathArgs<float> a = detail::make_args<float>(p, seed, n_paths, 0, nullptr);
+    const int64_t waves = (n_paths + kWave - 1) / kWave;
+    const int64_t n_part = waves * 2 * p.N;
+    hipLaunchKernelGGL(zero_kernel, dim3(static_cast<unsigned>((n_part + 255) / 256)), dim3(256), 0,
+                       st, gb.gpart, n_part);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    VjpArgs v;
+    v.xb = gb.vjp_xb;
+    v.part = gb.gpart;
+    VjpWeights wts{};
+    float w[LLL_N_MAX];
+    for (int i = 0; i < p.N; ++i) {
+        wts.g[i] = weights[i];
+        w[i] = static_cast<float>(weights[i] * p.delta[i]);
+    }
+    switch (p.nmax) {
+        case 8: e = launch_vjp_bucket<8>(a, g, v, w, st); break;
+        case 16: e = launch_vjp_bucket<16>(a, g, v, w, st); break;
+        case 24: e = launch_vjp_bucket<24>(a, g, v, w, st); break;
+        case 32: e = launch_vjp_bucket<32>(a, g, v, w, st); break;
+        case 40: e = launch_vjp_bucket<40>(a, g, v, w, st); break;
+        default: return hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) return e;
+    e = launch_reduce(p, n_paths, st);  // prices
+    if (e != hipSuccess) return e;
+    e = reduce_cols(gb.gpart, waves, 2 * p.N, gb.gchunks, gb.gsums, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(vjp_finalize_kernel, dim3(1), dim3(64), 0, st, gb.gsums, p.d.results,
+                       p.d.delta, p.d.L0, wts, p.N, p.S, p.B0_T1, n_paths, gb.vjp_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_greeks(const lll_plan &p, int64_t n_paths, uint64_t seed, hipStream_t st) {
+    using namespace adj;
+    const DeviceTables &d = p.d;
+    const GreeksBuffers &gb = p.g;
+    AdjArgs g;
+    hipError_t e = adjoint_setup(p, n_paths, seed, st, g);
+    if (e != hipSuccess) return e;
+    PathArgs<float> a = detail::make_args<float>(p, seed, n_paths, 0, nullptr);
     switch (p.nmax) {
         case 8: e = launch_adjoint_bucket<8>(a, g, st); break;
         case 16: e = launch_adjoint_bucket<16>(a, g, st); break;
@@ -159,15 +268,7 @@ hipError_t launch_greeks(const lll_plan &p, int64_t n_paths, uint64_t seed, hipS
     e = launch_reduce(p, n_paths, st);  // prices
     if (e != hipSuccess) return e;
     const int64_t waves = (n_paths + kWave - 1) / kWave;
-    const int cols = p.N * 2 * p.N;
-    const int64_t chunks = (waves + 255) / 256;
-    hipLaunchKernelGGL(reduce_cols_kernel, dim3(static_cast<unsigned>(chunks)), dim3(256), 0, st,
-                       gb.gpart, waves, cols, 256, gb.gchunks);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(reduce_cols_kernel, dim3(1), dim3(256), 0, st, gb.gchunks, chunks, cols,
-                       chunks, gb.gsums);
-    e = hipGetLastError();
+    e = reduce_cols(gb.gpart, waves, p.N * 2 * p.N, gb.gchunks, gb.gsums, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(greeks_finalize_kernel, dim3(1), dim3(64), 0, st, gb.gsums, d.results,
                        d.delta, d.L0, p.N, p.S, p.B0_T1, n_paths, gb.out);

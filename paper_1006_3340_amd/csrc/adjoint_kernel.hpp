@@ -167,6 +167,77 @@ __device__ __forceinline__ void reverse_step(const PathArgs<float> &a, const Adj
     }
 }
 
+// Adds w times the payoff adjoint of caplet c (strike 0; slot JC = off + c)
+// at its fixing date T_{c+1} to the state adjoint Xb and the L0 accumulators:
+// f = D (L_c - K)^+ with D = prod_{l>c}(1 + delta_l L_l).  Loads the fixing
+// state into X.
+template <int NMAX, int JC>
+__device__ __forceinline__ void seed_caplet(const PathArgs<float> &a, const AdjArgs &g, int64_t gl,
+                                            bool active, float w, float (&X)[NMAX],
+                                            float (&Xb)[NMAX], float *__restrict__ accL0) {
+    const int lane = threadIdx.x;
+    const int c = JC - a.off;
+    X[JC] = g.fix[static_cast<int64_t>(c) * g.n_paths + gl];
+#pragma unroll
+    for (int j = JC + 1; j < NMAX; ++j)
+        X[j] = g.ckpt[ckpt_row(a.N, c + 1, j - a.off) * g.n_paths + gl];
+    double D = 1.0;
+    float ellf[NMAX];
+#pragma unroll
+    for (int j = JC + 1; j < NMAX; ++j) {
+        const double L = a.L0s[j] * static_cast<double>(expf(X[j]));
+        D *= 1.0 + a.deltas[j] * L;
+        ellf[j] = static_cast<float>(a.deltas[j] * L / (1.0 + a.deltas[j] * L));
+    }
+    const double Lc = a.L0s[JC] * static_cast<double>(expf(X[JC]));
+    const double K = a.strikes[c * a.S];
+    const bool itm = active && (Lc > K);
+    const float dXc = itm ? w * static_cast<float>(D * Lc) : 0.0f;
+    const float dD = itm ? w * static_cast<float>(Lc - K) : 0.0f;
+    const float Df = static_cast<float>(D);
+    Xb[JC] += dXc;
+    accL0[lane] += dXc * static_cast<float>(g.inv_L0[JC]);
+#pragma unroll
+    for (int j = JC + 1; j < NMAX; ++j) {
+        const float t = dD * Df * ellf[j];
+        Xb[j] += t;
+        accL0[(j - JC) * kAdjBlock + lane] += t * static_cast<float>(g.inv_L0[j]);
+    }
+}
+
+// Reverse of period m for the slots JC .. NMAX-1: recompute the period from
+// its checkpoint, keeping every step's state in the scratch, then walk the
+// steps back, updating Xb from the adjoint at the period's end to the one at
+// its start.
+template <int NMAX, int JC>
+__device__ __forceinline__ void reverse_period(const PathArgs<float> &a, const AdjArgs &g, int m,
+                                               int64_t gl, bool active, uint32_t p_lo,
+                                               uint32_t p_hi, float (&X)[NMAX], float (&X1)[NMAX],
+                                               float (&Xb)[NMAX], float *__restrict__ accL0,
+                                               float *__restrict__ accV) {
+#pragma unroll
+    for (int j = JC; j < NMAX; ++j) X[j] = g.ckpt[ckpt_row(a.N, m, j - a.off) * g.n_paths + gl];
+    for (int js = 0; js < a.s; ++js) {
+        const int k = m * a.s + js;
+        const float dH = increment_f(a, k, m, p_lo, p_hi);
+        if (active) {
+#pragma unroll
+            for (int j = JC; j < NMAX; ++j)
+                g.scr[(static_cast<int64_t>(js) * NMAX + j) * g.n_paths + gl] = X[j];
+            g.scr_dh[static_cast<int64_t>(js) * g.n_paths + gl] = dH;
+        }
+        detail::step<float, NMAX, kFull, JC>(a, k, dH, X, X1);
+    }
+    for (int js = a.s - 1; js >= 0; --js) {
+        const int k = m * a.s + js;
+#pragma unroll
+        for (int j = JC; j < NMAX; ++j)
+            X[j] = g.scr[(static_cast<int64_t>(js) * NMAX + j) * g.n_paths + gl];
+        const float dH = g.scr_dh[static_cast<int64_t>(js) * g.n_paths + gl];
+        reverse_step<NMAX, JC>(a, g, k, dH, X, Xb, accL0, accV);
+    }
+}
+
 // Sweep of the caplet fixing in slot JC (rate c = JC - off, period c).
 template <int NMAX, int JC>
 __device__ __forceinline__ void sweep(const PathArgs<float> &a, const AdjArgs &g, int64_t gid, bool active,
@@ -183,7 +254,6 @@ __device__ __forceinline__ void sweep(const PathArgs<float> &a, const AdjArgs &g
         accL0[(j - JC) * kAdjBlock + lane] = 0.0f;
         accV[(j - JC) * kAdjBlock + lane] = 0.0f;
     }
-    // state at the fixing date T_{c+1}
     float X[NMAX], X1[NMAX], Xb[NMAX];
 #pragma unroll
     for (int j = 0; j < NMAX; ++j) {
@@ -191,65 +261,14 @@ __device__ __forceinline__ void sweep(const PathArgs<float> &a, const AdjArgs &g
         X1[j] = 0.0f;
         Xb[j] = 0.0f;
     }
-    X[JC] = g.fix[static_cast<int64_t>(c) * g.n_paths + gl];
-#pragma unroll
-    for (int j = JC + 1; j < NMAX; ++j)
-        X[j] = g.ckpt[ckpt_row(N, c + 1, j - a.off) * g.n_paths + gl];
-    // payoff adjoint, strike 0: f = D (L_c - K)^+
-    {
-        double D = 1.0;
-        float ellf[NMAX];
-#pragma unroll
-        for (int j = JC + 1; j < NMAX; ++j) {
-            const double L = a.L0s[j] * static_cast<double>(expf(X[j]));
-            D *= 1.0 + a.deltas[j] * L;
-            ellf[j] = static_cast<float>(a.deltas[j] * L / (1.0 + a.deltas[j] * L));
-        }
-        const double Lc = a.L0s[JC] * static_cast<double>(expf(X[JC]));
-        const double K = a.strikes[c * a.S];
-        const bool itm = active && (Lc > K);
-        const float dXc = itm ? static_cast<float>(D * Lc) : 0.0f;
-        const float dD = itm ? static_cast<float>(Lc - K) : 0.0f;
-        const float Df = static_cast<float>(D);
-        Xb[JC] = dXc;
-        accL0[lane] += dXc * static_cast<float>(g.inv_L0[JC]);
-#pragma unroll
-        for (int j = JC + 1; j < NMAX; ++j) {
-            const float t = dD * Df * ellf[j];
-            Xb[j] = t;
-            accL0[(j - JC) * kAdjBlock + lane] += t * static_cast<float>(g.inv_L0[j]);
-        }
-    }
+    seed_caplet<NMAX, JC>(a, g, gl, active, 1.0f, X, Xb, accL0);
     // skip the sweep when no lane of the wavefront has a nonzero adjoint
     bool any = false;
 #pragma unroll
     for (int j = JC; j < NMAX; ++j) any = any || (Xb[j] != 0.0f);
     if (__any(any)) {
-        for (int m = c; m >= 0; --m) {
-            // recompute period m from its checkpoint, keeping every step's state
-#pragma unroll
-            for (int j = JC; j < NMAX; ++j)
-                X[j] = g.ckpt[ckpt_row(N, m, j - a.off) * g.n_paths + gl];
-            for (int js = 0; js < a.s; ++js) {
-                const int k = m * a.s + js;
-                const float dH = increment_f(a, k, m, p_lo, p_hi);
-                if (active) {
-#pragma unroll
-                    for (int j = JC; j < NMAX; ++j)
-                        g.scr[(static_cast<int64_t>(js) * NMAX + j) * g.n_paths + gl] = X[j];
-                    g.scr_dh[static_cast<int64_t>(js) * g.n_paths + gl] = dH;
-                }
-                detail::step<float, NMAX, kFull, JC>(a, k, dH, X, X1);
-            }
-            for (int js = a.s - 1; js >= 0; --js) {
-                const int k = m * a.s + js;
-#pragma unroll
-                for (int j = JC; j < NMAX; ++j)
-                    X[j] = g.scr[(static_cast<int64_t>(js) * NMAX + j) * g.n_paths + gl];
-                const float dH = g.scr_dh[static_cast<int64_t>(js) * g.n_paths + gl];
-                reverse_step<NMAX, JC>(a, g, k, dH, X, Xb, accL0, accV);
-            }
-        }
+        for (int m = c; m >= 0; --m)
+            reverse_period<NMAX, JC>(a, g, m, gl, active, p_lo, p_hi, X, X1, Xb, accL0, accV);
     }
     // wavefront sums of this caplet's adjoints
     const int64_t wave = gid / kWave;
@@ -269,6 +288,65 @@ __device__ __forceinline__ void sweep(const PathArgs<float> &a, const AdjArgs &g
         }
 }
 
+// Vector-Jacobian product: one reverse sweep for sum_c g_c f_c.  The kernel of
+// period m (slot JC = off + m) continues the sweep from the end of period m:
+// it takes the state adjoint carried from period m+1 (xb, by rate), adds the
+// seed of caplet m (weight w_m = g_m delta_m) at its fixing, reverses the
+// period and stores the adjoint at the period's start; the wavefront sums of
+// its parameter adjoints are added to the per-wave partials (periods in
+// launch order, so the sums are deterministic).
+struct VjpArgs {
+    float *xb;      // [N][n_paths] state adjoint by rate, carried between periods
+    double *part;   // [waves][2N] sums of L0bar (first N) and vbar
+};
+
+template <int NMAX, int JC>
+__device__ __forceinline__ void vjp_period(const PathArgs<float> &a, const AdjArgs &g,
+                                           const VjpArgs &v, float w, int64_t gid, bool active,
+                                           float *__restrict__ accL0, float *__restrict__ accV) {
+    const int lane = threadIdx.x;
+    const int m = JC - a.off;
+    const int N = a.N;
+    const int64_t p = a.path_offset + gid;
+    const uint32_t p_lo = static_cast<uint32_t>(p);
+    const uint32_t p_hi = static_cast<uint32_t>(static_cast<uint64_t>(p) >> 32);
+    const int64_t gl = active ? gid : 0;
+#pragma unroll
+    for (int j = JC; j < NMAX; ++j) {
+        accL0[(j - JC) * kAdjBlock + lane] = 0.0f;
+        accV[(j - JC) * kAdjBlock + lane] = 0.0f;
+    }
+    float X[NMAX], X1[NMAX], Xb[NMAX];
+#pragma unroll
+    for (int j = 0; j < NMAX; ++j) {
+        X[j] = 0.0f;
+        X1[j] = 0.0f;
+        Xb[j] = 0.0f;
+    }
+    // rate m is fixed after period m: only the later rates carry an adjoint
+#pragma unroll
+    for (int j = JC + 1; j < NMAX; ++j)
+        Xb[j] = active ? v.xb[static_cast<int64_t>(j - a.off) * g.n_paths + gid] : 0.0f;
+    seed_caplet<NMAX, JC>(a, g, gl, active, w, X, Xb, accL0);
+    bool any = false;
+#pragma unroll
+    for (int j = JC; j < NMAX; ++j) any = any || (Xb[j] != 0.0f);
+    if (__any(any)) reverse_period<NMAX, JC>(a, g, m, gl, active, p_lo, p_hi, X, X1, Xb, accL0, accV);
+    if (active) {
+#pragma unroll
+        for (int j = JC; j < NMAX; ++j) v.xb[static_cast<int64_t>(j - a.off) * g.n_paths + gid] = Xb[j];
+    }
+    double *out = v.part + (gid / kWave) * 2 * N;
+    for (int j = JC; j < NMAX; ++j) {
+        const double l0 = detail::wave_sum(active ? accL0[(j - JC) * kAdjBlock + lane] : 0.0f);
+        const double vv = detail::wave_sum(active ? accV[(j - JC) * kAdjBlock + lane] : 0.0f);
+        if (lane == 0) {
+            out[j - a.off] += l0;
+            out[N + j - a.off] += vv;
+        }
+    }
+}
+
 // One launch per caplet (slot JC): each sweep is its own kernel so that its
 // register allocation covers only its own live set.
 template <int NMAX, int JC>
@@ -281,6 +359,17 @@ __global__ void __launch_bounds__(kAdjBlock) sweep_kernel(PathArgs<float> a, Adj
     const int64_t wave_first = gid - threadIdx.x;
     if (wave_first >= a.n_paths) return;
     sweep<NMAX, JC>(a, g, gid, gid < a.n_paths, accL0, accV);
+}
+
+template <int NMAX, int JC>
+__global__ void __launch_bounds__(kAdjBlock) vjp_period_kernel(PathArgs<float> a, AdjArgs g,
+                                                               VjpArgs v, float w) {
+    __shared__ float accL0[(NMAX - JC) * kAdjBlock];
+    __shared__ float accV[(NMAX - JC) * kAdjBlock];
+    const int64_t gid = static_cast<int64_t>(blockIdx.x) * kAdjBlock + threadIdx.x;
+    const int64_t wave_first = gid - threadIdx.x;
+    if (wave_first >= a.n_paths) return;
+    vjp_period<NMAX, JC>(a, g, v, w, gid, gid < a.n_paths, accL0, accV);
 }
 
 template <int NMAX>
@@ -302,6 +391,35 @@ hipError_t launch_sweep(std::integer_sequence<int, Js...>, int jc, dim3 grid,
                         const PathArgs<float> &a, const AdjArgs &g, hipStream_t st) {
     hipError_t e = hipErrorInvalidValue;
     (void)((jc == Js ? (e = launch_one_sweep<NMAX, Js>(grid, a, g, st), 0) : 0) + ...);
+    return e;
+}
+
+template <int NMAX, int JC>
+hipError_t launch_one_vjp(dim3 grid, const PathArgs<float> &a, const AdjArgs &g, const VjpArgs &v,
+                          float w, hipStream_t st) {
+    hipLaunchKernelGGL((vjp_period_kernel<NMAX, JC>), grid, dim3(kAdjBlock), 0, st, a, g, v, w);
+    return hipGetLastError();
+}
+
+template <int NMAX, int... Js>
+hipError_t launch_vjp(std::integer_sequence<int, Js...>, int jc, dim3 grid, const PathArgs<float> &a,
+                      const AdjArgs &g, const VjpArgs &v, float w, hipStream_t st) {
+    hipError_t e = hipErrorInvalidValue;
+    (void)((jc == Js ? (e = launch_one_vjp<NMAX, Js>(grid, a, g, v, w, st), 0) : 0) + ...);
+    return e;
+}
+
+// Forward pass with checkpoints, then the periods from the last to the first
+// (w[m] = weight of caplet m times delta_m; v.part must be zero).
+template <int NMAX>
+hipError_t launch_vjp_bucket(const PathArgs<float> &a, const AdjArgs &g, const VjpArgs &v,
+                             const float *w, hipStream_t st) {
+    const dim3 grid(static_cast<unsigned>((a.n_paths + kAdjBlock - 1) / kAdjBlock));
+    hipLaunchKernelGGL(forward_kernel<NMAX>, grid, dim3(kAdjBlock), 0, st, a, g);
+    hipError_t e = hipGetLastError();
+    for (int m = a.N - 1; m >= 0 && e == hipSuccess; --m)
+        e = launch_vjp<NMAX>(std::make_integer_sequence<int, NMAX>{}, a.off + m, grid, a, g, v, w[m],
+                             st);
     return e;
 }
 

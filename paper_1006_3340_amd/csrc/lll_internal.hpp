@@ -65,6 +65,8 @@ struct GreeksBuffers {
     double *inv_L0 = nullptr;
     float *ckpt = nullptr, *fix = nullptr, *scr = nullptr, *scr_dh = nullptr;
     double *gpart = nullptr, *gchunks = nullptr, *gsums = nullptr, *out = nullptr;
+    float *vjp_xb = nullptr;   // [N][paths] state adjoint carried between periods
+    double *vjp_out = nullptr; // [3N] price, sum_i g_i dP_i/dL0, sum_i g_i dP_i/dvol
 };
 }  // namespace lll
 
@@ -83,6 +85,7 @@ struct lll_plan {
     int64_t last_n_paths = 0, greeks_n_paths = 0;
     bool mlp_done = false;
     bool greeks_done = false;
+    bool vjp_done = false;
     bool executed = false;
     bool timing = false, timed = false;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -114,6 +117,8 @@ hipError_t launch_first_order_tables(const lll_plan &p, hipStream_t st);
 hipError_t greeks_alloc(lll_plan &p);
 void greeks_free(lll_plan &p);
 hipError_t launch_greeks(const lll_plan &p, int64_t n_paths, uint64_t seed, hipStream_t st);
+hipError_t launch_greeks_vjp(const lll_plan &p, int64_t n_paths, uint64_t seed,
+                             const double *weights, hipStream_t st);
 
 // mlp_host.hip
 void mlp_plan_free(lll_plan &p);
