@@ -354,6 +354,15 @@ int lll_batch_timing(lll_batch *batch, float *ms_host);
 
 int lll_batch_destroy(lll_batch *batch);
 
+/* One-shot batch: create, execute once with n_paths_each paths per structure,
+ * copy each structure's results and destroy (as lll_batch_create,
+ * lll_batch_execute and lll_batch_results).  price_host[i] receives structure
+ * i's [N_i][S_i] prices; stderr_host may be NULL, else stderr_host[i] is NULL
+ * or an [N_i][S_i] buffer.  Synchronous. */
+int lll_price_caplets_batched(const lll_term_structure *ts, int n_ts, int64_t n_paths_each,
+                              int scheme, uint64_t seed, double *const *price_host,
+                              double *const *stderr_host, void *stream);
+
 /* ---- inspection entry points (used by the parity tests) ---- */
 
 /* Philox-4x32-10 words computed on the device for n counters ctr_host[n][4]

@@ -30,7 +30,7 @@ EXPORTS = ["lll_version", "lll_last_error", "lll_plan_create", "lll_plan_execute
            "lll_plan_drift", "lll_plan_set_timing", "lll_plan_timing", "lll_batch_create",
            "lll_batch_execute", "lll_batch_results", "lll_batch_set_timing", "lll_batch_timing",
            "lll_batch_destroy", "lll_plan_greeks", "lll_plan_greeks_results", "lll_plan_greeks_vjp",
-           "lll_plan_greeks_vjp_results", "lll_caplet_greeks",
+           "lll_plan_greeks_vjp_results", "lll_caplet_greeks", "lll_price_caplets_batched",
            "lll_mlp_create", "lll_mlp_destroy", "lll_mlp_params", "lll_mlp_generate",
            "lll_mlp_info", "lll_mlp_set_box", "lll_mlp_pairs", "lll_mlp_train", "lll_mlp_eval",
            "lll_plan_execute_mlp", "lll_plan_mlp_stats"]
@@ -88,6 +88,9 @@ def load():
     lib.lll_plan_destroy.argtypes = [vp]
     lib.lll_price_caplets.argtypes = [ctypes.POINTER(TermStructureC), i64, i32, u64, i32, dp, dp,
                                       dp, vp]
+    dpp = ctypes.POINTER(dp)
+    lib.lll_price_caplets_batched.argtypes = [ctypes.POINTER(TermStructureC), i32, i64, i32, u64,
+                                              dpp, dpp, vp]
     lib.lll_philox.argtypes = [u32p, u32p, i64, u32p, vp]
     lib.lll_plan_increments.argtypes = [vp, i32, i64, i64, u64, dp, dp, vp]
     lib.lll_plan_tables.argtypes = [vp, dp, dp, dp, dp, dp, vp]
@@ -366,6 +369,23 @@ def price_caplets(ts, n_paths: int, scheme: int = FULL, seed: int = 1, precision
                                  int(precision), _dp(price), _dp(se), _dp(mart),
                                  stream_handle(stream)))
     return {"price": price, "stderr": se, "mart_resid": mart}
+
+
+def price_caplets_batched(structures, n_paths_each: int, scheme: int = FULL, seed: int = 1,
+                          stream=None) -> list:
+    """lll_price_caplets_batched: prices and standard errors of every structure
+    from one persistent launch."""
+    lib = load()
+    ts_c = [_TS(ts) for ts in structures]
+    arr = (TermStructureC * len(ts_c))(*[t.c for t in ts_c])
+    out = [{"price": np.zeros((ts.n_rates, ts.n_strikes)), "stderr": np.zeros((ts.n_rates, ts.n_strikes))}
+           for ts in structures]
+    dp = ctypes.POINTER(ctypes.c_double)
+    prices = (dp * len(out))(*[_dp(o["price"]) for o in out])
+    ses = (dp * len(out))(*[_dp(o["stderr"]) for o in out])
+    _check(lib.lll_price_caplets_batched(arr, len(ts_c), int(n_paths_each), int(scheme), int(seed),
+                                         prices, ses, stream_handle(stream)))
+    return out
 
 
 def _fp(a: Optional[np.ndarray]):

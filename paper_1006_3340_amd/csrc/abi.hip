@@ -534,6 +534,23 @@ int lll_batch_create(const lll_term_structure *ts, int n_ts, int64_t max_paths_e
     return LLL_OK;
 }
 
+int lll_price_caplets_batched(const lll_term_structure *ts, int n_ts, int64_t n_paths_each,
+                              int scheme, uint64_t seed, double *const *price_host,
+                              double *const *stderr_host, void *stream) {
+    if (!price_host) return fail(LLL_EINVAL, "price_host is NULL");
+    for (int i = 0; i < n_ts && ts; ++i)
+        if (!price_host[i]) return fail(LLL_EINVAL, "price_host[%d] is NULL", i);
+    lll_batch *b = nullptr;
+    int rc = lll_batch_create(ts, n_ts, n_paths_each, &b);
+    if (rc != LLL_OK) return rc;
+    rc = lll_batch_execute(b, scheme, n_paths_each, seed, stream);
+    for (int i = 0; i < n_ts && rc == LLL_OK; ++i)
+        rc = lll_batch_results(b, i, price_host[i], stderr_host ? stderr_host[i] : nullptr,
+                               nullptr, nullptr, nullptr, stream);
+    lll_batch_destroy(b);
+    return rc;
+}
+
 int lll_batch_set_timing(lll_batch *batch, int enable) {
     if (!batch) return fail(LLL_EINVAL, "batch is NULL");
     if (enable && !batch->ev[0]) {

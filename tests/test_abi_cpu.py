@@ -97,6 +97,12 @@ def test_batch_validation_errors():
     with pytest.raises(lll.LLLError) as ei:
         lll.Batch([ts.copy(L0=-ts.L0)], max_paths_each=64)
     assert ei.value.code == -1
+    # the one-shot batch needs its output buffers
+    import paper_1006_3340_amd._lib as L
+    lib = L.load()
+    t = L._TS(ts)
+    rc = lib.lll_price_caplets_batched(ctypes.byref(t.c), 1, 64, 0, 1, None, None, None)
+    assert rc == -1 and "price_host" in lib.lll_last_error().decode()
     # batches run the 40-slot path kernel: N = 41 is rejected before allocation
     big = workloads.make_structure(41, 0.25, 0.03, 2, lambda t, T, r: 0.1, [1.0])
     with pytest.raises(lll.LLLError) as ei:

@@ -309,6 +309,18 @@ def test_batched_matches_single_structure_launches(gpu_lib):
                 assert np.array_equal(got["n_itm"], ref["n_itm"]), (scheme, i)
 
 
+
+def test_one_shot_batched_matches_batch_api(gpu_lib):
+    structs = workloads.batched()[:5]
+    n = 1000
+    out = gpu_lib.price_caplets_batched(structs, n, PICARD, seed=4)
+    with gpu_lib.Batch(structs, max_paths_each=n) as b:
+        b.execute(PICARD, n, seed=4)
+        for i in range(len(structs)):
+            r = b.results(i)
+            assert np.array_equal(out[i]["price"], r["price"])
+            assert np.array_equal(out[i]["stderr"], r["stderr"])
+
 @pytest.mark.parametrize("idx", [0, 1, 2])
 def test_batched_subset_matches_oracle(gpu_lib, oracle_mod, idx):
     """Structures spanning the N range against the FP64 oracle of each alone."""
