@@ -460,6 +460,11 @@ def main(argv=None) -> int:
                      "achieved": fl_dom / (ms_dom / 1e3) / 1e12, "peak": PEAK_FP32 / 1e12,
                      "unit": "TFLOP/s", "frac": fl_dom / (ms_dom / 1e3) / PEAK_FP32,
                      "traffic": TRAFFIC_BYTES.get(kernel_hash(), {}).get(dom),
+                     # the quoted FP32 peak counts dual-issue packed FMAs, which
+                     # this build keeps out of its code: one FMA per lane and
+                     # cycle is the reachable ceiling
+                     "single_issue_peak": PEAK_FP32 / 2 / 1e12,
+                     "frac_of_single_issue": fl_dom / (ms_dom / 1e3) / (PEAK_FP32 / 2),
                      "kernel_hash": kernel_hash()},
         "schemes": per_scheme,
         "wall_s": wall,
