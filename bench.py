@@ -90,9 +90,17 @@ def cpu_baseline(ts, n_sample: int, schemes) -> dict:
         threads = r["threads"]
         total_steps += n_sample * ts.n_steps
     dt = time.perf_counter() - t0
+    # one host thread on a smaller sample (the per-core rate)
+    n1 = max(64, n_sample // 48)
+    t1 = time.perf_counter()
+    for name in schemes:
+        o.price_sums({"full": 0, "picard": 1}[name], n1, threads=1)
+    dt1 = time.perf_counter() - t1
     return {"value": total_steps / dt, "unit": "path-steps/s", "cores": threads, "kind": "oracle",
             "sample": f"{n_sample} paths x {ts.n_steps} steps x {len(schemes)} schemes "
-                      f"({'+'.join(schemes)}) of the same workload, {dt:.1f} s"}
+                      f"({'+'.join(schemes)}) of the same workload, {dt:.1f} s",
+            "one_thread": {"value": n1 * ts.n_steps * len(schemes) / dt1,
+                           "sample": f"{n1} paths, {dt1:.1f} s"}}
 
 
 def adjoint_flops_per_path(ts) -> int:

@@ -103,7 +103,10 @@ def test_mp_chunks_deterministic_and_split_range(gpu_lib):
         assert np.array_equal(np.concatenate([p1, p2]), pa)
 
 
-@pytest.mark.parametrize("N,s", [(1, 1), (1, 7), (2, 1), (9, 3), (17, 2), (41, 2), (64, 1)])
+# s > 16 splits a period into equal step chunks (17 -> 9 + 8 with one padded
+# step, 33 -> 3 x 11, 35 -> 12 + 12 + 11)
+@pytest.mark.parametrize("N,s", [(1, 1), (1, 7), (2, 1), (9, 3), (17, 2), (41, 2), (64, 1),
+                                 (5, 17), (3, 33), (4, 35)])
 def test_mp_shapes(gpu_lib, oracle_mod, N, s):
     ts = workloads.make_structure(N, 0.25, 0.02 + 0.001 * np.arange(N), s,
                                   workloads.exp_decay_vol(), [0.9, 1.0, 1.1])

@@ -38,6 +38,21 @@ def test_vjp_equals_weighted_jacobian(gpu_lib, wl, n):
             _check(r["vjp_vol"], w @ g["dP_dvol"])
 
 
+@pytest.mark.parametrize("N,s", [(1, 3), (2, 1), (9, 2), (17, 1)])
+def test_vjp_shapes(gpu_lib, N, s):
+    ts = workloads.make_structure(N, 0.25, 0.02 + 0.001 * np.arange(N), s,
+                                  workloads.exp_decay_vol(), [1.0])
+    n = 2048 + 17
+    w = np.linspace(-1.0, 2.0, N)
+    with gpu_lib.Plan(ts, precision=0, max_paths=n) as plan:
+        plan.greeks(n, seed=2)
+        g = plan.greeks_results()
+        plan.greeks_vjp(n, w, seed=2)
+        r = plan.greeks_vjp_results()
+    _check(r["vjp_L0"], w @ g["dP_dL0"])
+    _check(r["vjp_vol"], w @ g["dP_dvol"])
+
+
 def test_vjp_full_size_and_timing(gpu_lib):
     """N = 40, 2^20 paths: the vector-Jacobian product against g^T J, and its
     cost against the full Jacobian's (one sweep instead of N)."""
