@@ -96,7 +96,14 @@ def cpu_baseline(ts, n_sample: int, schemes) -> dict:
     for name in schemes:
         o.price_sums({"full": 0, "picard": 1}[name], n1, threads=1)
     dt1 = time.perf_counter() - t1
+    cpu = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": total_steps / dt, "unit": "path-steps/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu, "host_cpus": os.cpu_count(),
             "sample": f"{n_sample} paths x {ts.n_steps} steps x {len(schemes)} schemes "
                       f"({'+'.join(schemes)}) of the same workload, {dt:.1f} s",
             "one_thread": {"value": n1 * ts.n_steps * len(schemes) / dt1,
