@@ -428,6 +428,7 @@ def main(argv=None) -> int:
     for _ in range(3):
         one_step(rec)
     torch.cuda.synchronize()
+    fma_probe = lll.fp32_fma_peak()   # measured non-packed FP32 FMA ceiling, TFLOP/s
     if args.copy_mib > 0:
         src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -477,9 +478,11 @@ def main(argv=None) -> int:
                      "traffic": TRAFFIC_BYTES.get(kernel_hash(), {}).get(dom),
                      # the quoted FP32 peak counts dual-issue packed FMAs, which
                      # this build keeps out of its code: one FMA per lane and
-                     # cycle is the reachable ceiling
+                     # cycle is the reachable ceiling (quoted / 2), also measured
+                     # on this GPU by the library's FMA probe
                      "single_issue_peak": PEAK_FP32 / 2 / 1e12,
                      "frac_of_single_issue": fl_dom / (ms_dom / 1e3) / (PEAK_FP32 / 2),
+                     "fma_probe_tflops": fma_probe,
                      "kernel_hash": kernel_hash()},
         "schemes": per_scheme,
         "wall_s": wall,

@@ -365,6 +365,14 @@ int lll_price_caplets_batched(const lll_term_structure *ts, int n_ts, int64_t n_
 
 /* ---- inspection entry points (used by the parity tests) ---- */
 
+/* Measured roofline ceiling of the path kernels: the throughput (TFLOP/s,
+ * FMA = 2) of plain non-packed FP32 FMAs on the current device -- independent
+ * chains on every lane of a full grid, best of 3 timed runs.  The quoted FP32
+ * vector peak counts dual-issue packed FMAs, which this library does not
+ * generate.  Synchronous (waits for `stream`); allocates and frees a small
+ * buffer. */
+int lll_fp32_fma_peak(double *tflops_host, void *stream);
+
 /* Philox-4x32-10 words computed on the device for n counters ctr_host[n][4]
  * and keys key_host[n][2]; out_host[n][4]. */
 int lll_philox(const uint32_t *ctr_host, const uint32_t *key_host, int64_t n,

@@ -31,6 +31,7 @@ EXPORTS = ["lll_version", "lll_last_error", "lll_plan_create", "lll_plan_execute
            "lll_batch_execute", "lll_batch_results", "lll_batch_set_timing", "lll_batch_timing",
            "lll_batch_destroy", "lll_plan_greeks", "lll_plan_greeks_results", "lll_plan_greeks_vjp",
            "lll_plan_greeks_vjp_results", "lll_caplet_greeks", "lll_price_caplets_batched",
+           "lll_fp32_fma_peak",
            "lll_mlp_create", "lll_mlp_destroy", "lll_mlp_params", "lll_mlp_generate",
            "lll_mlp_info", "lll_mlp_set_box", "lll_mlp_pairs", "lll_mlp_train", "lll_mlp_eval",
            "lll_plan_execute_mlp", "lll_plan_mlp_stats"]
@@ -91,6 +92,7 @@ def load():
     dpp = ctypes.POINTER(dp)
     lib.lll_price_caplets_batched.argtypes = [ctypes.POINTER(TermStructureC), i32, i64, i32, u64,
                                               dpp, dpp, vp]
+    lib.lll_fp32_fma_peak.argtypes = [dp, vp]
     lib.lll_philox.argtypes = [u32p, u32p, i64, u32p, vp]
     lib.lll_plan_increments.argtypes = [vp, i32, i64, i64, u64, dp, dp, vp]
     lib.lll_plan_tables.argtypes = [vp, dp, dp, dp, dp, dp, vp]
@@ -369,6 +371,14 @@ def price_caplets(ts, n_paths: int, scheme: int = FULL, seed: int = 1, precision
                                  int(precision), _dp(price), _dp(se), _dp(mart),
                                  stream_handle(stream)))
     return {"price": price, "stderr": se, "mart_resid": mart}
+
+
+def fp32_fma_peak(stream=None) -> float:
+    """lll_fp32_fma_peak: measured non-packed FP32 FMA throughput, TFLOP/s."""
+    lib = load()
+    out = np.zeros(1)
+    _check(lib.lll_fp32_fma_peak(_dp(out), stream_handle(stream)))
+    return float(out[0])
 
 
 def price_caplets_batched(structures, n_paths_each: int, scheme: int = FULL, seed: int = 1,

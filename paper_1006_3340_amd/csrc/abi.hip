@@ -382,6 +382,13 @@ int lll_price_caplets(const lll_term_structure *ts, int64_t n_paths, int scheme,
     return rc;
 }
 
+int lll_fp32_fma_peak(double *tflops_host, void *stream) {
+    if (!tflops_host) return fail(LLL_EINVAL, "tflops_host is NULL");
+    hipError_t e = lll::measure_fma_peak(as_stream(stream), tflops_host);
+    if (e != hipSuccess) return hip_fail(e, "FMA probe");
+    return LLL_OK;
+}
+
 int lll_philox(const uint32_t *ctr_host, const uint32_t *key_host, int64_t n, uint32_t *out_host,
                void *stream) {
     if (!ctr_host || !key_host || !out_host) return fail(LLL_EINVAL, "NULL argument");

@@ -1,0 +1,66 @@
+// fma_probe.hip -- measured ceiling of the roofline: the throughput of plain
+// (non-packed) FP32 FMAs on the current GPU, the instruction the path kernels'
+// coupling recursion is made of.  Every thread runs 8 independent FMA chains
+// of kIters steps; 32 blocks of 256 threads per compute unit keep every SIMD
+// busy.  The quoted 157.3 TFLOP/s vector peak counts dual-issue packed FMAs,
+// which this library does not use.
+#include <hip/hip_runtime.h>
+
+#include "lll_internal.hpp"
+
+namespace lll {
+namespace {
+
+constexpr int kIters = 4096;
+constexpr int kChains = 8;
+
+__global__ void __launch_bounds__(256) fma_probe_kernel(float *__restrict__ out, float b, float c) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    float a[kChains];
+#pragma unroll
+    for (int j = 0; j < kChains; ++j) a[j] = t * 1e-7f + j * 1e-7f;
+    for (int i = 0; i < kIters; ++i) {
+#pragma unroll
+        for (int j = 0; j < kChains; ++j) a[j] = fmaf(a[j], b, c);
+    }
+    float s = 0.0f;
+#pragma unroll
+    for (int j = 0; j < kChains; ++j) s += a[j];
+    out[t] = s;  // keeps the chains live
+}
+
+}  // namespace
+
+hipError_t measure_fma_peak(hipStream_t st, double *tflops) {
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    const int blocks = cus * 32, threads = 256;
+    float *out = nullptr;
+    e = hipMalloc(&out, (size_t)blocks * threads * sizeof(float));
+    if (e != hipSuccess) return e;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    double best = 0.0;
+    for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {
+        e = hipEventRecord(e0, st);
+        if (e != hipSuccess) break;
+        hipLaunchKernelGGL(fma_probe_kernel, dim3(blocks), dim3(threads), 0, st, out, 0.999999f, 1e-7f);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        const double fl = (double)blocks * threads * kIters * kChains * 2.0;
+        if (e == hipSuccess && rep > 0 && ms > 0.0f) best = fmax(best, fl / (ms * 1e-3) / 1e12);
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(out);
+    *tflops = best;
+    return e;
+}
+
+}  // namespace lll

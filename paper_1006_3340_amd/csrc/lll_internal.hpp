@@ -141,6 +141,9 @@ void picard_mp_free(lll_plan &p);
 hipError_t launch_picard_mp(const lll_plan &p, int64_t n_paths, int64_t path_offset,
                             uint64_t seed, double *path_fix, hipStream_t st);
 
+// fma_probe.hip: throughput of plain FP32 FMAs (TFLOP/s, best of 3 timed runs)
+hipError_t measure_fma_peak(hipStream_t st, double *tflops);
+
 // paths.hip
 hipError_t launch_paths(const lll_plan &p, int scheme, int64_t n_paths, int64_t path_offset,
                         uint64_t seed, double *path_fix, hipStream_t st);
