@@ -191,14 +191,14 @@ int lll_price_caplets(const lll_term_structure *ts, int64_t n_paths, int scheme,
                       int precision, double *price_host, double *stderr_host,
                       double *mart_resid_host, void *stream);
 
-/* ---- pathwise adjoint (caplet Greeks) ---- */
+/* ---- pathwise adjoint (caplet and swaption Greeks) ---- */
 
 /* Enqueue a FULL-scheme pricing pass of paths 0 .. n_paths-1 on an FP32 plan
- * (NIG driver, LLL_CAPLETS; LLL_EUNSUPPORTED otherwise) together with the
- * pathwise adjoint of every caplet price
- * (strike 0) with respect to the initial forwards L(0, T_l) and to a parallel
+ * (NIG driver; LLL_EUNSUPPORTED otherwise) together with the pathwise adjoint
+ * of every product price (strike 0; caplets or the co-terminal swaptions of
+ * the plan's product) with respect to the initial forwards L(0, T_l) and to a parallel
  * shift of each rate's volatility curve lambda(., T_l) (all steps k).  The
- * forward pass checkpoints the live rates at every tenor date; each caplet's
+ * forward pass checkpoints the live rates at every tenor date; each product's
  * reverse sweep recomputes one accrual period at a time from its checkpoint.
  * B(0, T_1) is held fixed, so dP/dL0 includes the dependence of B(0, T_*) on
  * the forwards (paper Section 3.3, eq. (caplet)).  Checkpoint and scratch
@@ -207,16 +207,16 @@ int lll_price_caplets(const lll_term_structure *ts, int64_t n_paths, int scheme,
  * N > LLL_N_MAX.  Asynchronous. */
 int lll_plan_greeks(lll_plan *plan, int64_t n_paths, uint64_t seed, void *stream);
 
-/* Vector-Jacobian product of the same caplet prices (strike 0) with weights
+/* Vector-Jacobian product of the same product prices (strike 0) with weights
  * g = weights_host[N] (host, read before return): out_L0[l] = sum_i g_i
  * dP_i/dL(0,T_l) and out_vol[l] = sum_i g_i dP_i/dv_l, the quantities that
  * reverse-mode differentiation of a scalar function of the prices needs.  One
  * reverse sweep, from the last fixing date to t = 0, whose state adjoint is
- * seeded with g_i times the payoff adjoint of caplet i at its fixing date
- * (paper Section 3.3, eq. (caplet)); per accrual period one kernel recomputes
+ * seeded with g_i times the payoff adjoint of product i at its fixing date
+ * (paper Section 3.3, eq. (caplet); the swaption payoff of lll_product); per accrual period one kernel recomputes
  * the period from its tenor-date checkpoint and walks it back.  Cost: the
  * forward pass plus one recompute and one reverse pass, against one sweep per
- * caplet for the full Jacobian of lll_plan_greeks (same conventions, buffers
+ * product for the full Jacobian of lll_plan_greeks (same conventions, buffers
  * and restrictions; equal to g^T J up to FP32 summation order).
  * LLL_EINVAL for NULL or non-finite weights.  Asynchronous. */
 int lll_plan_greeks_vjp(lll_plan *plan, int64_t n_paths, uint64_t seed, const double *weights_host,
@@ -228,7 +228,7 @@ int lll_plan_greeks_vjp_results(lll_plan *plan, double *price_host, double *vjp_
                                 double *vjp_vol_host, void *stream);
 
 /* Wait for `stream` and copy the last Greeks pass: price_host[N] (strike 0),
- * dP_dL0_host[N][N] and dP_dvol_host[N][N], row = caplet, column = input rate.
+ * dP_dL0_host[N][N] and dP_dvol_host[N][N], row = product, column = input rate.
  * Any pointer may be NULL. */
 int lll_plan_greeks_results(lll_plan *plan, double *price_host, double *dP_dL0_host,
                             double *dP_dvol_host, void *stream);

@@ -630,8 +630,6 @@ static int greeks_prepare(lll_plan *plan, int64_t n_paths) {
         return fail(LLL_EUNSUPPORTED, "the adjoint runs on FP32 plans");
     if (plan->driver != LLL_DRIVER_NIG)
         return fail(LLL_EUNSUPPORTED, "the adjoint is implemented for the NIG driver");
-    if (plan->product != LLL_CAPLETS)
-        return fail(LLL_EUNSUPPORTED, "the adjoint differentiates caplets");
     if (plan->N > LLL_N_MAX)
         return fail(LLL_EUNSUPPORTED, "the adjoint handles N <= %d", LLL_N_MAX);
     if (n_paths < 1 || n_paths > plan->max_paths)

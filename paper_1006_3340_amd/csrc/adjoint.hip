@@ -62,13 +62,13 @@ __global__ void __launch_bounds__(64) setup_adjoint_tables_kernel(
     }
 }
 
-// dP_i/dL0_l = delta_i B(0,T_*) mean(L0bar) - P_i delta_l / (1 + delta_l L0_l)
+// dP_i/dL0_l = s_i B(0,T_*) mean(L0bar) - P_i delta_l / (1 + delta_l L0_l)
 // (the second term: B(0,T_*) = B(0,T_1) / prod_l (1 + delta_l L0_l) with B(0,T_1) held);
-// dP_i/dvol_l = delta_i B(0,T_*) mean(vbar).
+// dP_i/dvol_l = s_i B(0,T_*) mean(vbar); s_i = delta_i for caplets, 1 for swaptions.
 __global__ void __launch_bounds__(64) greeks_finalize_kernel(
     const double *__restrict__ gsums, const double *__restrict__ results,
     const double *__restrict__ delta, const double *__restrict__ L0, int N, int S, double B0_T1,
-    int64_t n_paths, double *__restrict__ out) {
+    int64_t n_paths, int product, double *__restrict__ out) {
     double prod_all = 1.0;
     for (int l = 0; l < N; ++l) prod_all *= 1.0 + delta[l] * L0[l];
     const double B0T = B0_T1 / prod_all;
@@ -77,7 +77,7 @@ __global__ void __launch_bounds__(64) greeks_finalize_kernel(
     for (int i = threadIdx.x; i < N; i += blockDim.x) {
         const double P = results[i * S];  // strike 0
         price[i] = P;
-        const double scale = delta[i] * B0T / n;
+        const double scale = (product == LLL_SWAPTIONS ? 1.0 : delta[i]) * B0T / n;
         for (int l = 0; l < N; ++l) {
             dL[i * N + l] = scale * gsums[(size_t)i * 2 * N + l] - P * delta[l] / (1.0 + delta[l] * L0[l]);
             dV[i * N + l] = scale * gsums[(size_t)i * 2 * N + N + l];
@@ -85,7 +85,8 @@ __global__ void __launch_bounds__(64) greeks_finalize_kernel(
     }
 }
 
-// The vector-Jacobian product from the swept sums (seeds g_i delta_i):
+// The vector-Jacobian product from the swept sums (seeds g_i s_i, s_i = delta_i
+// for caplets, 1 for swaptions):
 // sum_i g_i dP_i/dL0_l = B(0,T_*) mean(L0bar_l) - (sum_i g_i P_i) delta_l / (1 + delta_l L0_l),
 // sum_i g_i dP_i/dvol_l = B(0,T_*) mean(vbar_l); out = [price (strike 0), dL0, dvol].
 struct VjpWeights {
@@ -228,7 +229,7 @@ hipError_t launch_greeks_vjp(const lll_plan &p, int64_t n_paths, uint64_t seed,
     float w[LLL_N_MAX];
     for (int i = 0; i < p.N; ++i) {
         wts.g[i] = weights[i];
-        w[i] = static_cast<float>(weights[i] * p.delta[i]);
+        w[i] = static_cast<float>(weights[i] * (p.product == LLL_SWAPTIONS ? 1.0 : p.delta[i]));
     }
     switch (p.nmax) {
         case 8: e = launch_vjp_bucket<8>(a, g, v, w, st); break;
@@ -271,7 +272,7 @@ hipError_t launch_greeks(const lll_plan &p, int64_t n_paths, uint64_t seed, hipS
     e = reduce_cols(gb.gpart, waves, p.N * 2 * p.N, gb.gchunks, gb.gsums, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(greeks_finalize_kernel, dim3(1), dim3(64), 0, st, gb.gsums, d.results,
-                       d.delta, d.L0, p.N, p.S, p.B0_T1, n_paths, gb.out);
+                       d.delta, d.L0, p.N, p.S, p.B0_T1, n_paths, p.product, gb.out);
     return hipGetLastError();
 }
 

@@ -112,8 +112,8 @@ __device__ void forward(const PathArgs<float> &a, const AdjArgs &g, int64_t gid,
             for (int j = 0; j < NMAX; ++j) xf = (j == j0) ? X[j] : xf;
             g.fix[static_cast<int64_t>(m) * g.n_paths + gid] = xf;
         }
-        detail::dispatch_payoff<float, NMAX, LLL_CAPLETS>(std::make_integer_sequence<int, NMAX>{}, j0, a, m,
-                                             gid, active, X);
+        detail::dispatch_payoff<float, NMAX, detail::kAnyProduct>(
+            std::make_integer_sequence<int, NMAX>{}, j0, a, m, gid, active, X);
     }
 }
 
@@ -167,10 +167,15 @@ __device__ __forceinline__ void reverse_step(const PathArgs<float> &a, const Adj
     }
 }
 
-// Adds w times the payoff adjoint of caplet c (strike 0; slot JC = off + c)
-// at its fixing date T_{c+1} to the state adjoint Xb and the L0 accumulators:
-// f = D (L_c - K)^+ with D = prod_{l>c}(1 + delta_l L_l).  Loads the fixing
-// state into X.
+// Adds w times the payoff adjoint of product c (strike 0; slot JC = off + c)
+// at its fixing date T_{c+1} to the state adjoint Xb and the L0 accumulators,
+// and loads the fixing state into X.
+//   caplet:   f = D (L_c - K)^+, D = prod_{l>c}(1 + delta_l L_l);
+//   swaption: f = (Q - 1 - K A)^+, Q = prod_{l>=c} b_l, b_l = 1 + delta_l L_l,
+//             A = sum_{l>=c} delta_l prod_{j>l} b_j, so that with
+//             S_l = sum_{c<=m<l} delta_m prod_{j>m} b_j = sum_{c<=m<l} delta_m Q / prod_{c<=j<=m} b_j
+//             df/dX_l = ell_l (Q - K S_l) where the payoff is positive.
+// The direct L0 terms are df/dX_l / L(0, T_l) (L = L(0,T) e^X at fixed X).
 template <int NMAX, int JC>
 __device__ __forceinline__ void seed_caplet(const PathArgs<float> &a, const AdjArgs &g, int64_t gl,
                                             bool active, float w, float (&X)[NMAX],
@@ -181,6 +186,29 @@ __device__ __forceinline__ void seed_caplet(const PathArgs<float> &a, const AdjA
 #pragma unroll
     for (int j = JC + 1; j < NMAX; ++j)
         X[j] = g.ckpt[ckpt_row(a.N, c + 1, j - a.off) * g.n_paths + gl];
+    if (a.product == LLL_SWAPTIONS) {
+        double Q = 1.0, A = 0.0;
+#pragma unroll
+        for (int j = NMAX - 1; j >= JC; --j) {
+            const double b = 1.0 + a.deltas[j] * (a.L0s[j] * static_cast<double>(expf(X[j])));
+            A = fma(a.deltas[j], Q, A);
+            Q *= b;
+        }
+        const double K = a.strikes[c * a.S];
+        const bool itm = active && ((Q - 1.0) - K * A > 0.0);
+        double pre = 1.0, S = 0.0;
+#pragma unroll
+        for (int j = JC; j < NMAX; ++j) {
+            const double L = a.L0s[j] * static_cast<double>(expf(X[j]));
+            const double b = 1.0 + a.deltas[j] * L;
+            const float t = itm ? w * static_cast<float>(a.deltas[j] * L / b * (Q - K * S)) : 0.0f;
+            Xb[j] += t;
+            accL0[(j - JC) * kAdjBlock + lane] += t * static_cast<float>(g.inv_L0[j]);
+            pre *= b;
+            S = fma(a.deltas[j], Q / pre, S);
+        }
+        return;
+    }
     double D = 1.0;
     float ellf[NMAX];
 #pragma unroll

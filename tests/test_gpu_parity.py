@@ -367,13 +367,20 @@ def _greeks_structure(N=8, levels=None, L0=None):
                                     B0_T1=1.0 / (1.0 + 0.25 * 0.031))
 
 
-def _oracle_fd(oracle_mod, N, n, h):
-    """Central differences of the FP64 oracle's FULL caplet prices under common
-    random numbers: bumps of L(0,T_l) and of the vol level v_l (B(0,T_1) and
-    the absolute strikes held)."""
+def _swaption_greeks_structure(N=8):
+    """_greeks_structure pricing co-terminal payer swaptions struck at the
+    forward swap rates."""
+    return workloads.coterminal_swaptions(_greeks_structure(N), [1.0])
+
+
+def _oracle_fd(oracle_mod, N, n, h, product=0):
+    """Central differences of the FP64 oracle's FULL prices (caplets, or
+    co-terminal swaptions for product 1) under common random numbers: bumps of
+    L(0,T_l) and of the vol level v_l (B(0,T_1) and the absolute strikes
+    held)."""
     L0 = 0.03 + 0.001 * np.arange(1, N + 1)
     lv = np.full(N, 0.12)
-    K = _greeks_structure(N).strikes
+    K = (_swaption_greeks_structure(N) if product else _greeks_structure(N)).strikes
     JL = np.zeros((N, N)); JV = np.zeros((N, N))
     for l in range(N):
         for J, bump in ((JL, "L"), (JV, "v")):
@@ -381,7 +388,7 @@ def _oracle_fd(oracle_mod, N, n, h):
             for sgn in (+1, -1):
                 L = L0.copy(); v = lv.copy()
                 (L if bump == "L" else v)[l] += sgn * h
-                ts = _greeks_structure(N, levels=v, L0=L).copy(strikes=K)
+                ts = _greeks_structure(N, levels=v, L0=L).copy(strikes=K, product=product)
                 prices.append(oracle_mod.Oracle(ts, seed=1).price(FULL, n)["price"][:, 0])
             J[:, l] = (prices[0] - prices[1]) / (2 * h)
     return JL, JV
@@ -400,6 +407,30 @@ def test_greeks_match_oracle_finite_differences(gpu_lib, oracle_mod, h, rtol):
         assert np.all(np.abs(got - ref) <= rtol * np.abs(ref) + rtol * 1e-2 * scale), (got, ref)
     ref_price = oracle_mod.Oracle(ts, seed=1).price(FULL, n)["price"][:, 0]
     assert np.allclose(g["price"], ref_price, rtol=1e-4)
+
+
+def test_swaption_greeks_match_oracle_finite_differences(gpu_lib, oracle_mod):
+    """The payoff adjoint of f = (Q - 1 - K A)^+: the pathwise Greeks of
+    co-terminal swaptions against the oracle's common-random-number central
+    differences (same bar as the caplets')."""
+    N, n, h, rtol = 8, 2000, 1e-6, 2e-3
+    ts = _swaption_greeks_structure(N)
+    with gpu_lib.Plan(ts, precision=0, max_paths=n) as plan:
+        plan.greeks(n, seed=1)
+        g = plan.greeks_results()
+        w = np.linspace(-1.0, 1.5, N)
+        plan.greeks_vjp(n, w, seed=1)
+        r = plan.greeks_vjp_results()
+    JL, JV = _oracle_fd(oracle_mod, N, n, h, product=1)
+    for got, ref in ((g["dP_dL0"], JL), (g["dP_dvol"], JV)):
+        scale = np.max(np.abs(ref), axis=1, keepdims=True)
+        assert np.all(np.abs(got - ref) <= rtol * np.abs(ref) + rtol * 1e-2 * scale), (got, ref)
+    ref_price = oracle_mod.Oracle(ts, seed=1).price(FULL, n)["price"][:, 0]
+    assert np.allclose(g["price"], ref_price, rtol=1e-4)
+    # the single sweep seeded with w: w^T J up to FP32 summation order
+    for got, J in ((r["vjp_L0"], g["dP_dL0"]), (r["vjp_vol"], g["dP_dvol"])):
+        ref = w @ J
+        assert np.all(np.abs(got - ref) <= 1e-5 * np.max(np.abs(ref))), (got, ref)
 
 
 def test_greeks_full_size_structure_and_fourier(gpu_lib):
@@ -506,8 +537,8 @@ def test_swaptions_fp32_kernel_matches_oracle(gpu_lib, oracle_mod, wl, n_paths):
 
 
 def test_swaption_identities_on_gpu(gpu_lib):
-    """The last expiry's swaption is the last caplet (one-period swap); the
-    adjoint refuses swaption plans; batched and single launches agree."""
+    """The last expiry's swaption is the last caplet (one-period swap), in
+    price and in its Greeks row; batched and single launches agree."""
     ts = workloads.gpu_scale()
     sw = workloads.coterminal_swaptions(ts, [0.9, 1.0, 1.1])
     cap = ts.copy(strikes=sw.strikes.copy())
@@ -518,9 +549,14 @@ def test_swaption_identities_on_gpu(gpu_lib):
         p2.execute(FULL, n, seed=4)
         a, b = p1.results()["price"], p2.results()["price"]
         assert np.allclose(a[-1], b[-1], rtol=1e-12, atol=0)
-        with pytest.raises(gpu_lib.LLLError) as ei:
-            p1.greeks(n, seed=1)
-        assert ei.value.code == -5
+        p1.greeks(n, seed=1)
+        p2.greeks(n, seed=1)
+        ga, gb = p1.greeks_results(), p2.greeks_results()
+        for k in ("dP_dL0", "dP_dvol"):
+            # swaption seed delta L e^X (Q - K S) with S = 0, Q = b against the
+            # caplet's w D L with w = delta, D = 1: equal up to FP32 rounding
+            assert np.allclose(ga[k][-1], gb[k][-1], rtol=1e-5,
+                               atol=1e-6 * np.max(np.abs(gb[k][-1]))), k
     structs = [sw, workloads.coterminal_swaptions(workloads.plain_fp64(), [1.0])]
     with gpu_lib.Batch(structs, max_paths_each=4096) as bt:
         bt.execute(FULL, 4096, seed=2)

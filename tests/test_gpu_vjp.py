@@ -1,4 +1,4 @@
-"""Single-sweep vector-Jacobian product of the caplet prices (lll_plan_greeks_vjp).
+"""Single-sweep vector-Jacobian product of the caplet and swaption prices (lll_plan_greeks_vjp).
 
 It seeds one reverse sweep with the weights g_i at every fixing date, so it
 must equal g^T J of the per-caplet sweeps (lll_plan_greeks, pinned against the
@@ -20,10 +20,14 @@ def _check(got, ref, tol=1e-5):
     assert np.all(np.abs(got - ref) <= tol * scale), (np.max(np.abs(got - ref)) / scale, got, ref)
 
 
-@pytest.mark.parametrize("wl,n", [("adjoint_n40", 1 << 16), ("plain_n10", 4096), ("gpu_n20", 4096)])
-def test_vjp_equals_weighted_jacobian(gpu_lib, wl, n):
+@pytest.mark.parametrize("wl,n,product", [("adjoint_n40", 1 << 16, 0), ("plain_n10", 4096, 0),
+                                          ("gpu_n20", 4096, 0), ("adjoint_n40", 1 << 16, 1),
+                                          ("gpu_n20", 4096, 1)])
+def test_vjp_equals_weighted_jacobian(gpu_lib, wl, n, product):
     ts = workloads.WORKLOADS[wl]()
     N = ts.n_rates
+    if product == 1:
+        ts = workloads.coterminal_swaptions(ts, [1.0])
     if ts.n_strikes > 1:
         ts = ts.copy(strikes=ts.strikes[:, 1:2].copy())   # ATM as strike 0
     rng = np.random.default_rng(7)
@@ -82,8 +86,7 @@ def test_vjp_errors(gpu_lib):
         with pytest.raises(gpu_lib.LLLError) as ei:
             plan.greeks_vjp_results()                 # nothing run yet
         assert ei.value.code == -1
-    sw = workloads.coterminal_swaptions(ts)
-    with gpu_lib.Plan(sw, precision=0, max_paths=64) as plan:
+    with gpu_lib.Plan(ts, precision=1, max_paths=64) as plan:   # FP64 plan
         with pytest.raises(gpu_lib.LLLError) as ei:
             plan.greeks_vjp(64, np.ones(ts.n_rates))
         assert ei.value.code == -5
