@@ -1,7 +1,8 @@
-"""torch.autograd.Function over the pathwise caplet adjoint.
+"""torch.autograd.Function over the pathwise adjoint.
 
-``CapletPrice.apply(L0, vol_levels, ts, n_paths, seed)`` returns the caplet
-prices (strike 0 of each caplet) of the term structure ``ts`` with its initial
+``CapletPrice.apply(L0, vol_levels, ts, n_paths, seed)`` returns the product
+prices (strike 0 of each caplet, or of each co-terminal swaption when
+``ts.product`` is 1) of the term structure ``ts`` with its initial
 forwards replaced by ``L0`` and its vol curves shifted so that
 lambda(t, T_i) = vol_levels[i] + (ts.vol[k, i] - base_levels[i]) (a parallel
 shift of each rate's curve).  The forward pass is a FULL pricing pass; the

@@ -22,7 +22,10 @@
 //     Ebar_l    = Cbar_l W_q (P_l - 1) + ell_l P_l F_l,  lambdabar_l += x_q e^{lambda_l x_q} Ebar_l
 //     F_{l+1}   = (1 + ell_l E_{l,q}) F_l + Cbar_l W_q E_{l,q},     Cbar_l = -dt Xbar_l,
 // then Xbar_l += ellbar_l ell_l (1 - ell_l), L0bar_l += ellbar_l ell_l (1 - ell_l) / L(0, T_l),
-// lambdabar_l += Xbar_l (dH - kappa'(lambda_l) dt).
+// lambdabar_l += Xbar_l (dH - kappa'(lambda_l) dt).  The per-lane L0 accumulators
+// sum the unscaled increments ellbar_l ell_l (1 - ell_l); the factor 1 / L(0, T_l),
+// the same for every step, multiplies their wavefront sum (no per-step constant
+// held in registers).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -162,7 +165,7 @@ __device__ __forceinline__ void reverse_step(const PathArgs<float> &a, const Adj
     for (int j = JC; j < NMAX; ++j) {
         const float t = lb[j] * mdt * ell[j] * (1.0f - ell[j]);
         Xb[j] += t;
-        accL0[(j - JC) * kAdjBlock + lane] += t * static_cast<float>(g.inv_L0[j]);
+        accL0[(j - JC) * kAdjBlock + lane] += t;
         accV[(j - JC) * kAdjBlock + lane] += vb[j] * mdt;
     }
 }
@@ -175,7 +178,8 @@ __device__ __forceinline__ void reverse_step(const PathArgs<float> &a, const Adj
 //             A = sum_{l>=c} delta_l prod_{j>l} b_j, so that with
 //             S_l = sum_{c<=m<l} delta_m prod_{j>m} b_j = sum_{c<=m<l} delta_m Q / prod_{c<=j<=m} b_j
 //             df/dX_l = ell_l (Q - K S_l) where the payoff is positive.
-// The direct L0 terms are df/dX_l / L(0, T_l) (L = L(0,T) e^X at fixed X).
+// The direct L0 terms are df/dX_l / L(0, T_l) (L = L(0,T) e^X at fixed X); the
+// accumulators hold the df/dX_l terms, scaled by 1 / L(0, T_l) after the wave sum.
 template <int NMAX, int JC>
 __device__ __forceinline__ void seed_caplet(const PathArgs<float> &a, const AdjArgs &g, int64_t gl,
                                             bool active, float w, float (&X)[NMAX],
@@ -203,7 +207,7 @@ __device__ __forceinline__ void seed_caplet(const PathArgs<float> &a, const AdjA
             const double b = 1.0 + a.deltas[j] * L;
             const float t = itm ? w * static_cast<float>(a.deltas[j] * L / b * (Q - K * S)) : 0.0f;
             Xb[j] += t;
-            accL0[(j - JC) * kAdjBlock + lane] += t * static_cast<float>(g.inv_L0[j]);
+            accL0[(j - JC) * kAdjBlock + lane] += t;
             pre *= b;
             S = fma(a.deltas[j], Q / pre, S);
         }
@@ -224,12 +228,12 @@ __device__ __forceinline__ void seed_caplet(const PathArgs<float> &a, const AdjA
     const float dD = itm ? w * static_cast<float>(Lc - K) : 0.0f;
     const float Df = static_cast<float>(D);
     Xb[JC] += dXc;
-    accL0[lane] += dXc * static_cast<float>(g.inv_L0[JC]);
+    accL0[lane] += dXc;
 #pragma unroll
     for (int j = JC + 1; j < NMAX; ++j) {
         const float t = dD * Df * ellf[j];
         Xb[j] += t;
-        accL0[(j - JC) * kAdjBlock + lane] += t * static_cast<float>(g.inv_L0[j]);
+        accL0[(j - JC) * kAdjBlock + lane] += t;
     }
 }
 
@@ -302,7 +306,8 @@ __device__ __forceinline__ void sweep(const PathArgs<float> &a, const AdjArgs &g
     const int64_t wave = gid / kWave;
     double *out = g.gpart + (static_cast<int64_t>(wave) * N + c) * 2 * N;
     for (int j = JC; j < NMAX; ++j) {
-        const double l0 = detail::wave_sum(active ? accL0[(j - JC) * kAdjBlock + lane] : 0.0f);
+        const double l0 =
+            detail::wave_sum(active ? accL0[(j - JC) * kAdjBlock + lane] : 0.0f) * g.inv_L0[j];
         const double vv = detail::wave_sum(active ? accV[(j - JC) * kAdjBlock + lane] : 0.0f);
         if (lane == 0) {
             out[j - a.off] = l0;
@@ -366,7 +371,8 @@ __device__ __forceinline__ void vjp_period(const PathArgs<float> &a, const AdjAr
     }
     double *out = v.part + (gid / kWave) * 2 * N;
     for (int j = JC; j < NMAX; ++j) {
-        const double l0 = detail::wave_sum(active ? accL0[(j - JC) * kAdjBlock + lane] : 0.0f);
+        const double l0 =
+            detail::wave_sum(active ? accL0[(j - JC) * kAdjBlock + lane] : 0.0f) * g.inv_L0[j];
         const double vv = detail::wave_sum(active ? accV[(j - JC) * kAdjBlock + lane] : 0.0f);
         if (lane == 0) {
             out[j - a.off] += l0;

@@ -486,11 +486,12 @@ def test_greeks_full_size_structure_and_fourier(gpu_lib):
                     (kind, l, c, J[c, l], fd[c])
 
 
-def test_autograd_function(gpu_lib):
+@pytest.mark.parametrize("product", [0, 1])
+def test_autograd_function(gpu_lib, product):
     import torch
     from paper_1006_3340_amd.autograd import CapletPrice
     N = 8
-    ts = _greeks_structure(N)
+    ts = _swaption_greeks_structure(N) if product else _greeks_structure(N)
     base = np.full(N, 0.12)
     L0 = torch.tensor(ts.L0, dtype=torch.float64, requires_grad=True)
     lv = torch.tensor(base, dtype=torch.float64, requires_grad=True)
