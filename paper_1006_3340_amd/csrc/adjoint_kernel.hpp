@@ -87,8 +87,10 @@ __device__ __forceinline__ void dispatch_ckpt(std::integer_sequence<int, Js...>,
     (void)((j0 == Js ? (store_ckpt<NMAX, Js>(a, g, m, gid, active, X), 0) : 0) + ...);
 }
 
-// Forward FULL pass with checkpoints; also the price partials.
-template <int NMAX>
+// Forward FULL pass with checkpoints; also the price partials of PRODUCT
+// (LLL_CAPLETS or LLL_SWAPTIONS, fixed at compile time: the product's payoff
+// code is inlined at every fixing date).
+template <int NMAX, int PRODUCT>
 __device__ void forward(const PathArgs<float> &a, const AdjArgs &g, int64_t gid, bool active) {
     const int64_t p = a.path_offset + gid;
     const uint32_t p_lo = static_cast<uint32_t>(p);
@@ -115,8 +117,8 @@ __device__ void forward(const PathArgs<float> &a, const AdjArgs &g, int64_t gid,
             for (int j = 0; j < NMAX; ++j) xf = (j == j0) ? X[j] : xf;
             g.fix[static_cast<int64_t>(m) * g.n_paths + gid] = xf;
         }
-        detail::dispatch_payoff<float, NMAX, detail::kAnyProduct>(
-            std::make_integer_sequence<int, NMAX>{}, j0, a, m, gid, active, X);
+        detail::dispatch_payoff<float, NMAX, PRODUCT>(std::make_integer_sequence<int, NMAX>{}, j0,
+                                                      a, m, gid, active, X);
     }
 }
 
@@ -406,12 +408,12 @@ __global__ void __launch_bounds__(kAdjBlock) vjp_period_kernel(PathArgs<float> a
     vjp_period<NMAX, JC>(a, g, v, w, gid, gid < a.n_paths, accL0, accV);
 }
 
-template <int NMAX>
+template <int NMAX, int PRODUCT>
 __global__ void __launch_bounds__(kAdjBlock) forward_kernel(PathArgs<float> a, AdjArgs g) {
     const int64_t gid = static_cast<int64_t>(blockIdx.x) * kAdjBlock + threadIdx.x;
     const int64_t wave_first = gid - threadIdx.x;
     if (wave_first >= a.n_paths) return;
-    forward<NMAX>(a, g, gid, gid < a.n_paths);
+    forward<NMAX, PRODUCT>(a, g, gid, gid < a.n_paths);
 }
 
 template <int NMAX, int JC>
@@ -443,14 +445,22 @@ hipError_t launch_vjp(std::integer_sequence<int, Js...>, int jc, dim3 grid, cons
     return e;
 }
 
+template <int NMAX>
+hipError_t launch_forward(dim3 grid, const PathArgs<float> &a, const AdjArgs &g, hipStream_t st) {
+    if (a.product == LLL_SWAPTIONS)
+        hipLaunchKernelGGL((forward_kernel<NMAX, LLL_SWAPTIONS>), grid, dim3(kAdjBlock), 0, st, a, g);
+    else
+        hipLaunchKernelGGL((forward_kernel<NMAX, LLL_CAPLETS>), grid, dim3(kAdjBlock), 0, st, a, g);
+    return hipGetLastError();
+}
+
 // Forward pass with checkpoints, then the periods from the last to the first
 // (w[m] = weight of caplet m times delta_m; v.part must be zero).
 template <int NMAX>
 hipError_t launch_vjp_bucket(const PathArgs<float> &a, const AdjArgs &g, const VjpArgs &v,
                              const float *w, hipStream_t st) {
     const dim3 grid(static_cast<unsigned>((a.n_paths + kAdjBlock - 1) / kAdjBlock));
-    hipLaunchKernelGGL(forward_kernel<NMAX>, grid, dim3(kAdjBlock), 0, st, a, g);
-    hipError_t e = hipGetLastError();
+    hipError_t e = launch_forward<NMAX>(grid, a, g, st);
     for (int m = a.N - 1; m >= 0 && e == hipSuccess; --m)
         e = launch_vjp<NMAX>(std::make_integer_sequence<int, NMAX>{}, a.off + m, grid, a, g, v, w[m],
                              st);
@@ -461,8 +471,7 @@ hipError_t launch_vjp_bucket(const PathArgs<float> &a, const AdjArgs &g, const V
 template <int NMAX>
 hipError_t launch_adjoint_bucket(const PathArgs<float> &a, const AdjArgs &g, hipStream_t st) {
     const dim3 grid(static_cast<unsigned>((a.n_paths + kAdjBlock - 1) / kAdjBlock));
-    hipLaunchKernelGGL(forward_kernel<NMAX>, grid, dim3(kAdjBlock), 0, st, a, g);
-    hipError_t e = hipGetLastError();
+    hipError_t e = launch_forward<NMAX>(grid, a, g, st);
     for (int c = 0; c < a.N && e == hipSuccess; ++c)
         e = launch_sweep<NMAX>(std::make_integer_sequence<int, NMAX>{}, a.off + c, grid, a, g, st);
     return e;
