@@ -122,6 +122,38 @@ __device__ void forward(const PathArgs<float> &a, const AdjArgs &g, int64_t gid,
     }
 }
 
+// The same forward pass with the state in the block's LDS columns, as the
+// plain FP32 FULL path kernels of the 24- to 40-slot buckets run it (same
+// step and payoff code, so the same prices bit for bit): X, ell and the
+// coupling sums do not all fit the registers of two wavefronts per SIMD.
+template <int NMAX, int PRODUCT>
+__device__ void forward_lds(const PathArgs<float> &a, const AdjArgs &g, int64_t gid, bool active) {
+    float *xs = detail::state_lds<float, NMAX>() + threadIdx.x;
+    const int64_t p = a.path_offset + gid;
+    const uint32_t p_lo = static_cast<uint32_t>(p);
+    const uint32_t p_hi = static_cast<uint32_t>(static_cast<uint64_t>(p) >> 32);
+    float X1[NMAX];
+#pragma unroll
+    for (int j = 0; j < NMAX; ++j) {
+        xs[j * kBlock] = 0.0f;
+        X1[j] = 0.0f;
+    }
+    for (int m = 0; m < a.N; ++m) {
+        const int j0 = a.off + m;
+        if (active)
+            for (int j = j0; j < NMAX; ++j)
+                g.ckpt[ckpt_row(a.N, m, j - a.off) * g.n_paths + gid] = xs[j * kBlock];
+        for (int js = 0; js < a.s; ++js) {
+            const int k = m * a.s + js;
+            const float dH = increment_f(a, k, m, p_lo, p_hi);
+            detail::dispatch_step_lds<float, NMAX, kFull>(std::make_integer_sequence<int, NMAX>{}, j0,
+                                                          a, k, dH, xs, X1);
+        }
+        if (active) g.fix[static_cast<int64_t>(m) * g.n_paths + gid] = xs[j0 * kBlock];
+        detail::payoff_lds<float, NMAX, PRODUCT>(a, m, gid, active, xs, j0);
+    }
+}
+
 // Reverse of Euler step k for the slots JC .. NMAX-1, given the state X at the
 // start of the step and Xb = adjoint of the state at its end (updated in place
 // to the adjoint at the start).  Parameter adjoints go to the LDS accumulators.
@@ -445,12 +477,31 @@ hipError_t launch_vjp(std::integer_sequence<int, Js...>, int jc, dim3 grid, cons
     return e;
 }
 
+template <int NMAX, int PRODUCT>
+__global__ void __launch_bounds__(kBlock) forward_lds_kernel(PathArgs<float> a, AdjArgs g) {
+    const int64_t gid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    const int64_t wave_first = gid - (threadIdx.x % kWave);
+    if (wave_first >= a.n_paths) return;
+    forward_lds<NMAX, PRODUCT>(a, g, gid, gid < a.n_paths);
+}
+
 template <int NMAX>
 hipError_t launch_forward(dim3 grid, const PathArgs<float> &a, const AdjArgs &g, hipStream_t st) {
-    if (a.product == LLL_SWAPTIONS)
-        hipLaunchKernelGGL((forward_kernel<NMAX, LLL_SWAPTIONS>), grid, dim3(kAdjBlock), 0, st, a, g);
-    else
-        hipLaunchKernelGGL((forward_kernel<NMAX, LLL_CAPLETS>), grid, dim3(kAdjBlock), 0, st, a, g);
+    if constexpr (detail::kStateInLds<float, NMAX, kFull>) {
+        const dim3 lgrid(static_cast<unsigned>((a.n_paths + kBlock - 1) / kBlock));
+        if (a.product == LLL_SWAPTIONS)
+            hipLaunchKernelGGL((forward_lds_kernel<NMAX, LLL_SWAPTIONS>), lgrid, dim3(kBlock), 0, st,
+                               a, g);
+        else
+            hipLaunchKernelGGL((forward_lds_kernel<NMAX, LLL_CAPLETS>), lgrid, dim3(kBlock), 0, st, a,
+                               g);
+    } else {
+        if (a.product == LLL_SWAPTIONS)
+            hipLaunchKernelGGL((forward_kernel<NMAX, LLL_SWAPTIONS>), grid, dim3(kAdjBlock), 0, st, a,
+                               g);
+        else
+            hipLaunchKernelGGL((forward_kernel<NMAX, LLL_CAPLETS>), grid, dim3(kAdjBlock), 0, st, a, g);
+    }
     return hipGetLastError();
 }
 
