@@ -438,6 +438,17 @@ def main(argv=None) -> int:
     if not np.all(np.isfinite(res["price"])):
         print(json.dumps({"error": "non-finite prices"}))
         return 1
+    # host-to-host: the one-shot call (plan creation and HBM allocation, term
+    # structure upload, precompute, the FULL pass, results back to the host)
+    plan.execute(lll.FULL, n, seed=1, stream=stream)
+    full_price = plan.results(stream)["price"]
+    lll.price_caplets(ts, n, lll.FULL, seed=1, stream=stream)   # warmup
+    t1 = time.perf_counter()
+    one = lll.price_caplets(ts, n, lll.FULL, seed=1, stream=stream)
+    host_ms = (time.perf_counter() - t1) * 1e3
+    if not np.allclose(one["price"], full_price, rtol=1e-12, atol=0):
+        print(json.dumps({"error": "one-shot prices differ from the plan's"}))
+        return 1
 
     path_steps = n * ts.n_steps * len(schemes) * args.steps
     value = path_steps / elapsed
@@ -486,6 +497,8 @@ def main(argv=None) -> int:
                      "kernel_hash": kernel_hash()},
         "schemes": per_scheme,
         "wall_s": wall,
+        "host_io": {"call": "lll_price_caplets (one FULL pass, host buffers in and out)",
+                    "ms": host_ms, "path_steps_per_s": n * ts.n_steps / (host_ms / 1e3)},
     }
     out["reference_schemes"] = bench_reference_schemes(lll, plan, ts, n, stream)
     out["swaptions"] = bench_swaptions(lll, stream)
