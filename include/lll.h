@@ -26,7 +26,17 @@
  *               (group of 4 paths, period, quadrature node) instead of one
  *               path per lane.  The same estimator as LLL_PICARD (equal up to
  *               FP32 summation order) for runs with few paths and many rates;
- *               FP32 plans, NIG driver, N up to LLL_N_MAX_MP.
+ *               FP32 plans, NIG driver, N up to LLL_N_MAX_MP;
+ *   LLL_EXACT   the LLL_FULL estimator with the drift taken from the exact
+ *               expansion of the product over the subsets U of the later
+ *               rates (Section 3.2, eq. (product)): coupling of rate i =
+ *               sum_U prod_{l in U} ell_l prod_{l>i, l not in U}(1 - ell_l)
+ *               [kappa(lambda_i + lambda_U) - kappa(lambda_U) - kappa(lambda_i)],
+ *               closed-form cumulants and no quadrature (the paper's full
+ *               solution); 2^(N-1-i) terms for rate i, so N up to
+ *               LLL_N_MAX_EXACT; both precisions and drivers.  Its cumulant
+ *               table, s (2^(N+1) - 2 - N) entries in the plan precision, is
+ *               allocated on the first LLL_EXACT execute and kept by the plan.
  *
  * driven by a normal inverse Gaussian Lévy process (Section 4) or, as a
  * special case, by a Brownian motion.  The jump integral of the drift is the
@@ -66,6 +76,7 @@ extern "C" {
                                LLL_PICARD_MP), of batches, Greeks and the surrogate */
 #define LLL_N_MAX_MP 64     /* largest N of a plan (N > LLL_N_MAX: LLL_PICARD_MP only) */
 #define LLL_N_MAX_FP64 24   /* largest N for the FP64 path kernel */
+#define LLL_N_MAX_EXACT 20  /* largest N of LLL_EXACT (2^(N-m) - 1 drift terms per step) */
 #define LLL_S_MAX 8         /* largest number of strikes per caplet */
 #define LLL_Q 64            /* quadrature nodes of the coupling integral */
 #define LLL_NSTAT(S) (3 * (S) + 2) /* path statistics per caplet */
@@ -97,7 +108,8 @@ typedef enum {
     LLL_FROZEN = 2,
     LLL_FIRST_ORDER = 3,
     LLL_SECOND_ORDER = 4,
-    LLL_PICARD_MP = 5
+    LLL_PICARD_MP = 5,
+    LLL_EXACT = 6
 } lll_scheme;
 typedef enum { LLL_DRIVER_NIG = 0, LLL_DRIVER_BROWNIAN = 1 } lll_driver;
 typedef enum { LLL_FP32 = 0, LLL_FP64 = 1 } lll_precision;

@@ -5,11 +5,11 @@ The computation lives in the HIP library ``liblll.so`` behind the C ABI of
 package does not load the library; the first call does, and raises if the
 library is missing.
 """
-from ._lib import (FIRST_ORDER, FP32, FP64, FROZEN, FULL, N_MAX, N_MAX_MP,  # noqa: F401
-                   PICARD, PICARD_MP, SECOND_ORDER,
+from ._lib import (EXACT, FIRST_ORDER, FP32, FP64, FROZEN, FULL, N_MAX, N_MAX_EXACT,  # noqa: F401
+                   N_MAX_MP, PICARD, PICARD_MP, SECOND_ORDER,
                    Batch, LLLError, Mlp, Plan, caplet_greeks, load, philox, price_caplets,
                    price_caplets_batched, fp32_fma_peak,
                    version)
 
 SCHEMES = {"full": FULL, "picard": PICARD, "frozen": FROZEN, "first_order": FIRST_ORDER,
-           "second_order": SECOND_ORDER, "picard_mp": PICARD_MP}
+           "second_order": SECOND_ORDER, "picard_mp": PICARD_MP, "exact": EXACT}

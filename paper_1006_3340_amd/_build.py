@@ -13,7 +13,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblll.so")
 SOURCES = ["abi.hip", "precompute.hip", "paths.hip", "batched.hip", "adjoint.hip",
            "mlp_train.hip", "mlp_path.hip", "mlp_host.hip", "picard_mp.hip",
-           "fma_probe.hip"] + sorted(
+           "fma_probe.hip", "exact.hip"] + sorted(
     f for f in os.listdir(CSRC) if f.startswith(("bucket_", "adjoint_b")) and f.endswith(".hip"))
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

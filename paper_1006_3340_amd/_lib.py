@@ -19,10 +19,10 @@ LIB_PATH = os.path.join(_HERE, "liblll.so")
 LLL_OK = 0
 STATUS = {0: "LLL_OK", -1: "LLL_EINVAL", -2: "LLL_EMOMENT", -3: "LLL_ENOMEM", -4: "LLL_EHIP",
           -5: "LLL_EUNSUPPORTED", -6: "LLL_ENUMERIC"}
-FULL, PICARD, FROZEN, FIRST_ORDER, SECOND_ORDER, PICARD_MP = 0, 1, 2, 3, 4, 5
+FULL, PICARD, FROZEN, FIRST_ORDER, SECOND_ORDER, PICARD_MP, EXACT = 0, 1, 2, 3, 4, 5, 6
 CAPLETS, SWAPTIONS = 0, 1
 FP32, FP64 = 0, 1
-N_MAX, N_MAX_MP, N_MAX_FP64, S_MAX, Q = 40, 64, 24, 8, 64
+N_MAX, N_MAX_MP, N_MAX_FP64, N_MAX_EXACT, S_MAX, Q = 40, 64, 24, 20, 8, 64
 
 EXPORTS = ["lll_version", "lll_last_error", "lll_plan_create", "lll_plan_execute",
            "lll_plan_results", "lll_plan_sums", "lll_plan_partials", "lll_plan_destroy",

@@ -113,7 +113,7 @@ hipError_t dalloc(T **p, size_t n) {
 
 void free_tables(lll::DeviceTables &d) {
     void *ptrs[] = {d.tenor, d.delta, d.L0, d.vol, d.strikes, d.x, d.w, d.kappa, d.E, d.b0,
-                    d.steps, d.lam_pm, d.ew, d.lam, d.drift0, d.frozen, d.dt, d.cinv, d.k2, d.L0s,
+                    d.steps, d.lam_pm, d.ew, d.lam, d.drift0, d.frozen, d.dt, d.cinv, d.k2, d.kex, d.L0s,
                     d.deltas, d.partials, d.chunks, d.sums, d.results};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -268,7 +268,7 @@ int lll_plan_destroy(lll_plan *plan) {
 int lll_plan_execute(lll_plan *plan, int scheme, int64_t n_paths, int64_t path_offset,
                      uint64_t seed, double *path_fix_dev, void *stream) {
     if (!plan) return fail(LLL_EINVAL, "plan is NULL");
-    if (scheme < LLL_FULL || scheme > LLL_PICARD_MP)
+    if (scheme < LLL_FULL || scheme > LLL_EXACT)
         return fail(LLL_EINVAL, "unknown scheme %d", scheme);
     if (n_paths < 1 || n_paths > plan->max_paths)
         return fail(LLL_EINVAL, "n_paths=%lld outside 1..%lld", (long long)n_paths,
@@ -287,6 +287,19 @@ int lll_plan_execute(lll_plan *plan, int scheme, int64_t n_paths, int64_t path_o
         hipError_t ea = lll::picard_mp_alloc(*plan);
         if (ea != hipSuccess) return fail(LLL_ENOMEM, "PICARD_MP buffers: %s", hipGetErrorString(ea));
     }
+    const bool exact = scheme == LLL_EXACT;
+    if (exact && plan->N > LLL_N_MAX_EXACT)
+        return fail(LLL_EUNSUPPORTED, "LLL_EXACT sums 2^(N-1-i) terms per rate: N=%d > %d",
+                    plan->N, LLL_N_MAX_EXACT);
+    if (exact && !plan->d.kex) {
+        const size_t esz = plan->precision == LLL_FP64 ? sizeof(double) : sizeof(float);
+        hipError_t ea =
+            hipMalloc(&plan->d.kex, (size_t)lll::exact_table_entries(plan->N, plan->s) * esz);
+        if (ea != hipSuccess) {
+            plan->d.kex = nullptr;
+            return fail(LLL_ENOMEM, "exact-drift table: %s", hipGetErrorString(ea));
+        }
+    }
     if (scheme == LLL_FIRST_ORDER && !plan->d.k2) {
         const size_t esz = plan->precision == LLL_FP64 ? sizeof(double) : sizeof(float);
         hipError_t ea = hipMalloc(&plan->d.k2, (size_t)plan->K * plan->nmax * plan->nmax * esz);
@@ -303,8 +316,9 @@ int lll_plan_execute(lll_plan *plan, int scheme, int64_t n_paths, int64_t path_o
     if (e != hipSuccess) return hip_fail(e, "precompute launch");
     if (t) e = hipEventRecord(plan->ev[1], st);
     if (e == hipSuccess)
-        e = mp ? lll::launch_picard_mp(*plan, n_paths, path_offset, seed, path_fix_dev, st)
-               : lll::launch_paths(*plan, scheme, n_paths, path_offset, seed, path_fix_dev, st);
+        e = mp      ? lll::launch_picard_mp(*plan, n_paths, path_offset, seed, path_fix_dev, st)
+            : exact ? lll::launch_exact(*plan, n_paths, path_offset, seed, path_fix_dev, st)
+                    : lll::launch_paths(*plan, scheme, n_paths, path_offset, seed, path_fix_dev, st);
     if (e != hipSuccess) return hip_fail(e, "path kernel launch");
     if (t) e = hipEventRecord(plan->ev[2], st);
     if (e == hipSuccess) e = lll::launch_reduce(*plan, n_paths, st);

@@ -1,0 +1,112 @@
+"""LLL_EXACT: the FULL estimator with the drift of the exact subset expansion.
+
+The expansion (paper Section 3.2, eq. (product)) and the oracle's quadrature
+drift are the same drift: the oracle's is pinned to the subset sum to 1e-11
+relative (test_oracle_drift.py::test_drift_vs_exact_subset_expansion).  So
+the GPU's EXACT prices are compared with the oracle's FULL prices on the same
+random numbers: FP64 plans to 1e-9 relative (the two drifts differ by the
+rule's ~1e-11, FP64 arithmetic otherwise), FP32 plans at the FP32 bar of the
+other schemes (1e-4, deep out-of-the-money floor as in _check_prices); per
+path the FP64 EXACT fixings equal the FP64 FULL kernel's to 1e-10.
+"""
+import numpy as np
+import pytest
+
+import workloads
+
+from test_gpu_parity import _check_prices
+
+pytestmark = pytest.mark.gpu
+
+FULL, EXACT = 0, 6
+EINVAL, EUNSUPPORTED = -1, -5
+
+
+@pytest.mark.parametrize("wl,n_paths", [("plain_n10", 5000), ("kluge_n9", 3001), ("gpu_n20", 300)])
+def test_exact_fp64_matches_oracle_full(gpu_lib, oracle_mod, wl, n_paths):
+    ts = workloads.WORKLOADS[wl]()
+    ref = oracle_mod.Oracle(ts, seed=1).price(FULL, n_paths)
+    with gpu_lib.Plan(ts, precision=1, max_paths=n_paths) as plan:
+        plan.execute(EXACT, n_paths, seed=1)
+        got = plan.results()
+    assert np.all(np.abs(got["n_itm"] - ref["n_itm"]) <= 1)
+    assert np.allclose(got["price"], ref["price"], rtol=1e-9, atol=1e-300)
+    assert np.allclose(got["mart_resid"], ref["mart_resid"], rtol=0, atol=1e-11)
+
+
+@pytest.mark.parametrize("wl,n_paths", [("plain_n10", 10000), ("gpu_n20", 2000), ("kluge_n9", 3001)])
+def test_exact_fp32_matches_oracle_full(gpu_lib, oracle_mod, wl, n_paths):
+    ts = workloads.WORKLOADS[wl]()
+    ref = oracle_mod.Oracle(ts, seed=1).price(FULL, n_paths)
+    with gpu_lib.Plan(ts, precision=0, max_paths=n_paths) as plan:
+        plan.execute(EXACT, n_paths, seed=1)
+        got = plan.results()
+    _check_prices(got, ref, ts, 1e-4)
+
+
+def test_exact_paths_equal_full_paths_fp64(gpu_lib):
+    import torch
+    ts = workloads.plain_fp64()
+    n = 1000 + 13
+    N = ts.n_rates
+    fa = torch.empty((n, 2 * N), dtype=torch.float64, device="cuda")
+    fb = torch.empty((n, 2 * N), dtype=torch.float64, device="cuda")
+    with gpu_lib.Plan(ts, precision=1, max_paths=n) as plan:
+        plan.execute(FULL, n, seed=4, path_fix=fa)
+        plan.execute(EXACT, n, seed=4, path_fix=fb)
+    torch.cuda.synchronize()
+    fa, fb = fa.cpu().numpy(), fb.cpu().numpy()
+    assert np.all(np.abs(fb / fa - 1.0) < 1e-10)
+
+
+# N = 1 (no coupling), M <= 4 later rates only (N <= 5), the first register
+# block plus one or more enumerated bits (N = 6, 9, 17), and N = 20 itself
+@pytest.mark.parametrize("N,s", [(1, 3), (2, 2), (5, 2), (6, 2), (9, 1), (17, 1), (20, 1)])
+def test_exact_shapes(gpu_lib, oracle_mod, N, s):
+    ts = workloads.make_structure(N, 0.5, 0.02 + 0.002 * np.arange(N), s,
+                                  workloads.exp_decay_vol(), [0.9, 1.0, 1.1])
+    n = 517
+    ref = oracle_mod.Oracle(ts, seed=2).price(FULL, n)
+    with gpu_lib.Plan(ts, precision=1, max_paths=n) as plan:
+        plan.execute(EXACT, n, seed=2)
+        got = plan.results()
+    assert np.allclose(got["price"], ref["price"], rtol=1e-9, atol=1e-300)
+
+
+def test_exact_brownian_and_zero_vol(gpu_lib, oracle_mod):
+    tb = workloads.brownian(N=6)
+    ref = oracle_mod.Oracle(tb, seed=1).price(FULL, 3000)
+    with gpu_lib.Plan(tb, precision=1, max_paths=3000) as plan:
+        plan.execute(EXACT, 3000)
+        assert np.allclose(plan.results()["price"], ref["price"], rtol=1e-10, atol=1e-300)
+    ts = workloads.make_structure(7, 0.5, 0.03 + 0.004 * np.arange(7), 4, lambda t, T, r: 0.0,
+                                  [0.7, 1.0, 1.3])
+    B = ts.B0_T1 / np.cumprod(1.0 + ts.delta * ts.L0)
+    exact = ts.delta[:, None] * B[:, None] * np.maximum(ts.L0[:, None] - ts.strikes, 0.0)
+    for prec in (0, 1):
+        with gpu_lib.Plan(ts, precision=prec, max_paths=300) as plan:
+            plan.execute(EXACT, 300)
+            assert np.allclose(plan.results()["price"], exact, rtol=1e-12, atol=1e-18)
+
+
+def test_exact_swaptions(gpu_lib, oracle_mod):
+    ts = workloads.coterminal_swaptions(workloads.plain_fp64(), [0.8, 1.0, 1.2])
+    ref = oracle_mod.Oracle(ts, seed=3).price(FULL, 4000)
+    for prec, rtol in ((1, 1e-9), (0, 1e-4)):
+        with gpu_lib.Plan(ts, precision=prec, max_paths=4000) as plan:
+            plan.execute(EXACT, 4000, seed=3)
+            got = plan.results()
+        _check_prices(got, ref, ts, rtol)
+
+
+def test_exact_errors(gpu_lib):
+    ts = workloads.make_structure(21, 0.25, 0.03, 1, workloads.exp_decay_vol(), [1.0])
+    with gpu_lib.Plan(ts, precision=0, max_paths=64) as plan:
+        with pytest.raises(gpu_lib.LLLError) as ei:
+            plan.execute(EXACT, 64)
+        assert ei.value.code == EUNSUPPORTED
+        plan.execute(FULL, 64)                     # the plan is still usable
+    with gpu_lib.Batch([workloads.plain_fp64()], max_paths_each=64) as bt:
+        with pytest.raises(gpu_lib.LLLError) as ei:
+            bt.execute(EXACT, 64)
+        assert ei.value.code == EINVAL
