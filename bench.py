@@ -288,6 +288,59 @@ def bench_kluge(lll, stream) -> dict:
     return out
 
 
+def exact_flops_per_path(ts) -> int:
+    """Algorithmic flops of LLL_EXACT per path: per step of period m the
+    2^{N-m} - 1 subset terms of the live rates (one FMA each) plus the update
+    and the increment, as for FULL."""
+    N, s = ts.n_rates, ts.steps_per_period
+    return sum(s * (2 * ((1 << (N - m)) - 1) + 8 * (N - m) + 40) for m in range(N))
+
+
+# The paper's own timing of its full solution (exact drift) on the example of
+# its Section 4: N = 9, 10^4 paths, 5 steps per period, Matlab on an 8-process
+# Intel i7 (another machine: context, not a target).
+PAPER_FULL_SOLUTION_S = 141.0
+
+
+def bench_exact(lll, stream) -> dict:
+    """LLL_EXACT (drift of the exact subset expansion, no quadrature): the
+    paper's example at its own size in FP64 (beside the paper's 141 s), and
+    the benchmark workload (N = 20, 2^16 paths, FP32) against FULL on the same
+    paths."""
+    out = {}
+    ts = workloads.kluge_example()
+    n = 10000
+    with lll.Plan(ts, precision=lll.FP64, max_paths=n) as plan:
+        plan.set_timing(True)
+        plan.execute(lll.EXACT, n, seed=1, stream=stream)   # warmup (allocates the table)
+        plan.execute(lll.EXACT, n, seed=1, stream=stream)
+        t = plan.timing()
+        pe = plan.results(stream)["price"]
+        plan.execute(lll.FULL, n, seed=1, stream=stream)
+        pf = plan.results(stream)["price"]
+    ms = t["precompute"] + t["paths"] + t["reduce"]
+    out["kluge_n9_fp64_10000"] = {
+        "ms": ms, "path_kernel_ms": t["paths"], "path_steps_per_s": n * ts.n_steps / (ms / 1e3),
+        "paper_full_solution_s": PAPER_FULL_SOLUTION_S,
+        "max_rel_diff_vs_full": float(np.max(np.abs(pe[pf > 0] / pf[pf > 0] - 1)))}
+    ts = workloads.gpu_scale()
+    n = 1 << 16
+    with lll.Plan(ts, precision=lll.FP32, max_paths=n) as plan:
+        plan.set_timing(True)
+        plan.execute(lll.EXACT, n, seed=1, stream=stream)   # warmup
+        plan.execute(lll.EXACT, n, seed=1, stream=stream)
+        ms = plan.timing()["paths"]
+        pe = plan.results(stream)["price"]
+        plan.execute(lll.FULL, n, seed=1, stream=stream)
+        pf = plan.results(stream)["price"]
+    fl = exact_flops_per_path(ts) * n
+    out["gpu_n20_fp32_65536"] = {
+        "path_kernel_ms": ms, "path_steps_per_s": n * ts.n_steps / (ms / 1e3),
+        "fp32_tflops": fl / (ms / 1e3) / 1e12, "frac_fp32_peak": fl / (ms / 1e3) / PEAK_FP32,
+        "max_rel_diff_vs_full": float(np.max(np.abs(pe[pf > 0] / pf[pf > 0] - 1)))}
+    return out
+
+
 def bench_swaptions(lll, stream, n: int = 1 << 20) -> dict:
     """Co-terminal payer swaptions on the benchmark workload (strikes 0.8, 1, 1.2
     x forward swap rate): path-kernel time per scheme (the multi-rate payoff is
@@ -385,6 +438,8 @@ def main(argv=None) -> int:
                     help="also time the maturity-parallel PICARD layout (1) or not (0)")
     ap.add_argument("--kluge", type=int, default=1,
                     help="also reproduce the paper's example (implied-volatility errors, FP64)")
+    ap.add_argument("--exact", type=int, default=1,
+                    help="also time LLL_EXACT (the paper's example and N=20 at 2^16 paths)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (a kernel of "
                          "known traffic for calibrating HBM counters)")
@@ -513,6 +568,8 @@ def main(argv=None) -> int:
         out["maturity_parallel"] = bench_maturity_parallel(lll, stream)
     if args.kluge:
         out["kluge"] = bench_kluge(lll, stream)
+    if args.exact:
+        out["exact"] = bench_exact(lll, stream)
     if args.cpu_sample > 0:
         out["cpu_baseline"] = cpu_baseline(ts, args.cpu_sample, schemes)
     plan.close()
