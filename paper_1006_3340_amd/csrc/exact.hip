@@ -27,7 +27,8 @@
 // are formed once per rate and step, and the remaining rates are enumerated in
 // binary order (t) with a stack of prefix products P_b = prod over the bits
 // >= b of t, so that every p_U is a product of at most M rounded factors.  The
-// table rows are wave-uniform, so they are scalar loads.
+// table rows are the same for every lane: a rate's first 16 entries are scalar
+// loads, the rest pass through the wavefront's LDS in 1 KiB chunks.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -44,6 +45,22 @@ using detail::cptr;
 using detail::PathArgs;
 
 constexpr int kLo = 4;  // later rates whose products are formed in registers
+
+// Coefficients beyond the first 16 of a rate are staged through the
+// wavefront's own LDS buffers in chunks of 1 KiB (64 lanes x 16 B), loaded
+// kAhead chunks ahead with coalesced vector loads: wave-uniform scalar loads
+// of the same rows left the kernel waiting on memory latency.
+constexpr int kAhead = 3;
+template <typename Real>
+constexpr int kPer = 16 / sizeof(Real);  // values per lane and chunk
+template <typename Real>
+constexpr int kChunk = kWave * kPer<Real>;
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // Entries of step k's table before step k (period m = k / s, js = k % s).
 __host__ __device__ inline int64_t exact_step_base(int N, int s, int k) {
@@ -94,9 +111,10 @@ __global__ void __launch_bounds__(256) exact_table_kernel(const double *__restri
 }
 
 // sum_U (prod_{l in U} r_l) K_J(U) over the subsets U of the slots after J,
-// kj = the table entries of slot J at this step.
+// kj = the table entries of slot J at this step, wbuf = the wavefront's two
+// LDS chunk buffers.
 template <typename Real, int NMAX, int J>
-__device__ __forceinline__ Real subset_sum(const Real (&r)[NMAX], cptr<Real> kj) {
+__device__ __forceinline__ Real subset_sum(const Real (&r)[NMAX], cptr<Real> kj, Real *wbuf) {
     constexpr int M = NMAX - 1 - J;
     constexpr int h = M < kLo ? M : kLo;
     constexpr int H = M - h;
@@ -112,27 +130,85 @@ __device__ __forceinline__ Real subset_sum(const Real (&r)[NMAX], cptr<Real> kj)
         for (int e = 0; e < (1 << h); ++e) sum = fma(plo[e], kj[e], sum);
         return sum;
     } else {
-        // P[b] = prod over the set bits b' >= b of t of r of slot J+1+kLo+b'
-        Real P[H + 1];
+        // t = 2^hm u + v: v's (up to two) bits in registers (qm), u's bits on
+        // the stack P[b] = prod over the set bits b' >= b of u of r of slot
+        // J+1+kLo+hm+b'
+        constexpr int hm = H < 2 ? H : 2;
+        constexpr int Hs = H - hm;
+        Real qm[1 << hm];
+        qm[0] = Real(1);
 #pragma unroll
-        for (int b = 0; b <= H; ++b) P[b] = Real(1);
+        for (int b = 0; b < hm; ++b)
+#pragma unroll
+            for (int v = 0; v < (1 << b); ++v) qm[v | (1 << b)] = qm[v] * r[J + 1 + kLo + b];
+        Real P[Hs + 1];
+#pragma unroll
+        for (int b = 0; b <= Hs; ++b) P[b] = Real(1);
+        constexpr int n = 1 << M;                      // entries of slot J
+        constexpr int chunk = kChunk<Real>;
+        constexpr int nch = n > chunk ? n / chunk : 1;  // n is a multiple of chunk
+        constexpr int per = n > chunk ? chunk : n;      // entries per chunk
+        constexpr int tpc = per / (1 << kLo);           // blocks of 16 per chunk
+        const int lane = threadIdx.x % kWave;
+        // value i of a lane is entry i * 64 + lane of its chunk
+        Real pre[kAhead][kPer<Real>];
+#pragma unroll
+        for (int d = 0; d < kAhead; ++d)
+#pragma unroll
+            for (int i = 0; i < kPer<Real>; ++i) {
+                const int pos = i * kWave + lane;
+                pre[d][i] = (d < nch && pos < per) ? kj[static_cast<size_t>(d) * chunk + pos] : Real(0);
+            }
         Real total = Real(0);
-        for (int t = 0; t < (1 << H); ++t) {
-            const cptr<Real> kt = kj + static_cast<size_t>(t) * (1 << kLo);
-            Real inner = Real(0);
+        int u = 0;
+#pragma unroll 1
+        for (int c = 0; c < nch; ++c) {
+            Real *buf = wbuf + (c & 1) * chunk;
 #pragma unroll
-            for (int e = 0; e < (1 << kLo); ++e) inner = fma(plo[e], kt[e], inner);
-            total = fma(P[0], inner, total);
-            // t -> t + 1: bit cb is set, the bits below it are cleared
-            const int cb = __builtin_ctz(static_cast<unsigned>(t + 1));
+            for (int i = 0; i < kPer<Real>; ++i) {
+                const int pos = i * kWave + lane;
+                if (pos < per) buf[pos] = pre[0][i];
+            }
 #pragma unroll
-            for (int b = H - 1; b >= 0; --b) {
-                if (b == cb)
-                    P[b] = P[b + 1] * r[J + 1 + kLo + b];
-                else if (b < cb)
-                    P[b] = P[b + 1];
+            for (int d = 0; d + 1 < kAhead; ++d)
+#pragma unroll
+                for (int i = 0; i < kPer<Real>; ++i) pre[d][i] = pre[d + 1][i];
+            const int cn = c + kAhead;
+#pragma unroll
+            for (int i = 0; i < kPer<Real>; ++i) {
+                const int pos = i * kWave + lane;
+                pre[kAhead - 1][i] =
+                    (cn < nch && pos < per) ? kj[static_cast<size_t>(cn) * chunk + pos] : Real(0);
+            }
+            wave_sync();  // the chunk's LDS values are visible to every lane
+#pragma unroll 1
+            for (int tt = 0; tt < tpc; tt += 1 << hm, ++u) {
+                // 2^hm blocks of 16, each as four independent FMA chains (one
+                // wavefront per SIMD is common here, so long chains would
+                // leave the ALU waiting)
+                Real grp = Real(0);
+#pragma unroll
+                for (int v = 0; v < (1 << hm); ++v) {
+                    const Real *kt = buf + (tt + v) * (1 << kLo);
+                    Real in4[4] = {Real(0), Real(0), Real(0), Real(0)};
+#pragma unroll
+                    for (int e = 0; e < (1 << kLo); ++e)
+                        in4[e & 3] = fma(plo[e], kt[e], in4[e & 3]);
+                    grp = fma(qm[v], (in4[0] + in4[1]) + (in4[2] + in4[3]), grp);
+                }
+                total = fma(P[0], grp, total);
+                // u -> u + 1: bit cb is set, the bits below it are cleared
+                const int cb = __builtin_ctz(static_cast<unsigned>(u + 1));
+#pragma unroll
+                for (int b = Hs - 1; b >= 0; --b) {
+                    if (b == cb)
+                        P[b] = P[b + 1] * r[J + 1 + kLo + hm + b];
+                    else if (b < cb)
+                        P[b] = P[b + 1];
+                }
             }
         }
+        wave_sync();  // the last reads are done before the buffers are reused
         return total;
     }
 }
@@ -142,20 +218,20 @@ __device__ __forceinline__ Real subset_sum(const Real (&r)[NMAX], cptr<Real> kj)
 template <typename Real, int NMAX, int J, int J0>
 __device__ __forceinline__ void exact_rates(const PathArgs<Real> &a, cptr<Real> kstep, int k,
                                             Real dH, const Real (&r)[NMAX], const Real (&om)[NMAX],
-                                            Real q, Real (&X)[NMAX]) {
+                                            Real q, Real (&X)[NMAX], Real *wbuf) {
     if constexpr (J >= J0) {
         constexpr int64_t off = (static_cast<int64_t>(1) << (NMAX - J0)) -
                                 (static_cast<int64_t>(1) << (NMAX - J));
-        const Real C = q * subset_sum<Real, NMAX, J>(r, kstep + off);
+        const Real C = q * subset_sum<Real, NMAX, J>(r, kstep + off, wbuf);
         const Real dt = a.dt[k];
         X[J] += fma(a.lam[(size_t)k * NMAX + J], dH, fma(-C, dt, a.drift0[(size_t)k * NMAX + J]));
-        exact_rates<Real, NMAX, J - 1, J0>(a, kstep, k, dH, r, om, q * om[J], X);
+        exact_rates<Real, NMAX, J - 1, J0>(a, kstep, k, dH, r, om, q * om[J], X, wbuf);
     }
 }
 
 template <typename Real, int NMAX, int J0>
 __device__ __forceinline__ void exact_step(const PathArgs<Real> &a, cptr<Real> kstep, int k, Real dH,
-                                           Real (&X)[NMAX]) {
+                                           Real (&X)[NMAX], Real *wbuf) {
     Real r[NMAX], om[NMAX];
 #pragma unroll
     for (int j = J0; j < NMAX; ++j) {
@@ -163,18 +239,20 @@ __device__ __forceinline__ void exact_step(const PathArgs<Real> &a, cptr<Real> k
         r[j] = Real(1) / ce;                     // ell / (1 - ell) = delta L
         om[j] = ce / (Real(1) + ce);             // 1 - ell
     }
-    exact_rates<Real, NMAX, NMAX - 1, J0>(a, kstep, k, dH, r, om, Real(1), X);
+    exact_rates<Real, NMAX, NMAX - 1, J0>(a, kstep, k, dH, r, om, Real(1), X, wbuf);
 }
 
 template <typename Real, int NMAX, int... Js>
 __device__ __forceinline__ void dispatch_exact_step(std::integer_sequence<int, Js...>, int j0,
                                                     const PathArgs<Real> &a, cptr<Real> kstep,
-                                                    int k, Real dH, Real (&X)[NMAX]) {
-    (void)((j0 == Js ? (exact_step<Real, NMAX, Js>(a, kstep, k, dH, X), 0) : 0) + ...);
+                                                    int k, Real dH, Real (&X)[NMAX], Real *wbuf) {
+    (void)((j0 == Js ? (exact_step<Real, NMAX, Js>(a, kstep, k, dH, X, wbuf), 0) : 0) + ...);
 }
 
 template <typename Real, int NMAX, int PRODUCT>
 __global__ void __launch_bounds__(kBlock) exact_kernel(PathArgs<Real> a, cptr<Real> kex) {
+    __shared__ Real kbuf[kBlock / kWave][2 * kChunk<Real>];  // per wavefront, two chunks
+    Real *wbuf = kbuf[threadIdx.x / kWave];
     const int64_t gid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     const int64_t wave_first = gid - (threadIdx.x % kWave);
     if (wave_first >= a.n_paths) return;  // whole wavefront past the end
@@ -196,7 +274,7 @@ __global__ void __launch_bounds__(kBlock) exact_kernel(PathArgs<Real> a, cptr<Re
         const Real dH = static_cast<Real>(increment(w, cst, a.beta, brownian, nullptr));
         const int j0 = a.off + m;
         dispatch_exact_step<Real, NMAX>(std::make_integer_sequence<int, NMAX>{}, j0, a,
-                                        kex + exact_step_base(a.N, a.s, k), k, dH, X);
+                                        kex + exact_step_base(a.N, a.s, k), k, dH, X, wbuf);
         if (++js == a.s) {
             detail::dispatch_payoff<Real, NMAX, PRODUCT>(std::make_integer_sequence<int, NMAX>{}, j0,
                                                          a, m, gid, active, X);
