@@ -271,15 +271,17 @@ def bench_kluge(lll, stream) -> dict:
     """The paper's numerical example on the GPU (FP64 kernels): caplet
     implied-volatility differences of each scheme against FULL (strikes
     0.8..1.2 x forward), at the paper's 10^4 paths and at 2^20 paths, next to
-    the numbers the paper reports (its strike grid and random numbers differ)."""
+    the numbers the paper reports (its strike grid and random numbers differ).
+    EXACT, the drift of the exact subset expansion, shows how far FULL's
+    64-node rule is from the paper's own full solution."""
     from paper_1006_3340_amd import quotes
     ts = workloads.kluge_example()
     out = {"workload": ts.name, "strikes": "0.8..1.2 x forward", "paper_bp": PAPER_KLUGE_BP}
-    names = {1: "picard", 2: "frozen", 3: "first_order", 4: "second_order"}
+    names = {1: "picard", 2: "frozen", 3: "first_order", 4: "second_order", 6: "exact"}
     for n in (10000, 1 << 20):
         with lll.Plan(ts, precision=lll.FP64, max_paths=n) as plan:
             iv = {}
-            for s in range(5):
+            for s in (0, 1, 2, 3, 4, 6):
                 plan.execute(s, n, seed=1, stream=stream)
                 iv[s] = quotes.caplet_implied_vols(ts, plan.results(stream)["price"])
         out[f"paths_{n}"] = {names[s]: {"max_bp": float(np.nanmax(np.abs(iv[s] - iv[0]) * 1e4)),
