@@ -27,8 +27,9 @@
 // are formed once per rate and step, and the remaining rates are enumerated in
 // binary order (t) with a stack of prefix products P_b = prod over the bits
 // >= b of t, so that every p_U is a product of at most M rounded factors.  The
-// table rows are the same for every lane: a rate's first 16 entries are scalar
-// loads, the rest pass through the wavefront's LDS in 1 KiB chunks.
+// table rows are the same for every lane: a rate with at most 16 entries reads
+// them as scalar loads, a longer one through the wavefront's LDS in 1 KiB
+// chunks.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -46,10 +47,11 @@ using detail::PathArgs;
 
 constexpr int kLo = 4;  // later rates whose products are formed in registers
 
-// Coefficients beyond the first 16 of a rate are staged through the
-// wavefront's own LDS buffers in chunks of 1 KiB (64 lanes x 16 B), loaded
-// kAhead chunks ahead with coalesced vector loads: wave-uniform scalar loads
-// of the same rows left the kernel waiting on memory latency.
+// The coefficients of a rate with more than four later rates (more than 16
+// entries) are staged through the wavefront's own LDS buffers in chunks of
+// 1 KiB (64 lanes x 16 B), loaded kAhead chunks ahead with coalesced vector
+// loads: wave-uniform scalar loads of the same rows left the kernel waiting on
+// memory latency.
 constexpr int kAhead = 3;
 template <typename Real>
 constexpr int kPer = 16 / sizeof(Real);  // values per lane and chunk
