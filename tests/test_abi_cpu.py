@@ -108,3 +108,18 @@ def test_batch_validation_errors():
     with pytest.raises(lll.LLLError) as ei:
         lll.Batch([ts, big], max_paths_each=64)
     assert ei.value.code == -1 and "structure 1" in str(ei.value)
+
+
+def test_binding_constants_match_the_header():
+    """Scheme numbers and size limits of the binding are the header's."""
+    import paper_1006_3340_amd as lll
+    import paper_1006_3340_amd._lib as L
+    text = open(os.path.join(ROOT, "include", "lll.h")).read()
+    enum = dict((k, int(v)) for k, v in re.findall(r"\bLLL_([A-Z_0-9]+) = (\d+)", text))
+    for name in ("FULL", "PICARD", "FROZEN", "FIRST_ORDER", "SECOND_ORDER", "PICARD_MP", "EXACT"):
+        assert getattr(L, name) == enum[name], name
+        assert lll.SCHEMES[name.lower()] == enum[name], name
+    defines = dict((k, int(v)) for k, v in re.findall(r"#define LLL_([A-Z_0-9]+) (\d+)", text))
+    assert (L.N_MAX, L.N_MAX_MP, L.N_MAX_FP64, L.N_MAX_EXACT, L.S_MAX, L.Q) == (
+        defines["N_MAX"], defines["N_MAX_MP"], defines["N_MAX_FP64"], defines["N_MAX_EXACT"],
+        defines["S_MAX"], defines["Q"])
