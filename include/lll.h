@@ -203,6 +203,32 @@ int lll_price_caplets(const lll_term_structure *ts, int64_t n_paths, int scheme,
                       int precision, double *price_host, double *stderr_host,
                       double *mart_resid_host, void *stream);
 
+/* ---- pricing without device allocation ---- */
+
+/* Size of the library's static device workspace (bytes per GPU). */
+#define LLL_STATIC_WORKSPACE_BYTES (64u << 20)
+
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: the same
+ * pass as lll_price_caplets (same arguments, same kernels, the same prices
+ * bit for bit) with every device buffer taken from one static workspace of
+ * LLL_STATIC_WORKSPACE_BYTES that each GPU holds from the first call on it
+ * until the process ends.  Calls no hipMalloc or hipFree.  The inputs are
+ * copied into the workspace on `stream`; the call waits for `stream` before
+ * it returns the results to the host buffers.
+ * Schemes LLL_FULL .. LLL_SECOND_ORDER (LLL_EUNSUPPORTED for LLL_PICARD_MP and
+ * LLL_EXACT), N <= LLL_N_MAX (FP64: N <= LLL_N_MAX_FP64).  The workspace needed,
+ * about 8 (K N Q + ceil(n_paths / 64) N (3 S + 2)) bytes plus the plan-precision
+ * step tables (K = N steps_per_period), must fit LLL_STATIC_WORKSPACE_BYTES:
+ * larger passes get LLL_EINVAL, with the size in the message, before any
+ * device work (the N = 20, 400-step, 3-strike workload fits up to ~2.0 M paths).
+ * Every call on a GPU shares that GPU's workspace: calls that overlap on one
+ * GPU (from several threads, or on unordered streams) race and must be
+ * serialised by the caller. */
+int lll_price_caplets_static(const lll_term_structure *ts, int64_t n_paths, int scheme,
+                             uint64_t seed, int precision, double *price_host,
+                             double *stderr_host, double *mart_resid_host, void *stream);
+
 /* ---- pathwise adjoint (caplet and swaption Greeks) ---- */
 
 /* Enqueue a FULL-scheme pricing pass of paths 0 .. n_paths-1 on an FP32 plan

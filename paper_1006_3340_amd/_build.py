@@ -13,7 +13,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblll.so")
 SOURCES = ["abi.hip", "precompute.hip", "paths.hip", "batched.hip", "adjoint.hip",
            "mlp_train.hip", "mlp_path.hip", "mlp_host.hip", "picard_mp.hip",
-           "fma_probe.hip", "exact.hip"] + sorted(
+           "fma_probe.hip", "exact.hip", "noalloc.hip"] + sorted(
     f for f in os.listdir(CSRC) if f.startswith(("bucket_", "adjoint_b")) and f.endswith(".hip"))
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -31,8 +31,18 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 PATH_FLAGS = ["-mllvm", "-disable-machine-licm"]
 
 
-def _compile(src: str) -> str:
+def _headers_mtime() -> float:
+    heads = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hpp")]
+    heads += [os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))]
+    return max(os.path.getmtime(h) for h in heads + [os.path.abspath(__file__)])
+
+
+def _compile(src: str, force: bool = True) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+    if not force and os.path.exists(obj):
+        t = os.path.getmtime(obj)
+        if t > os.path.getmtime(os.path.join(CSRC, src)) and t > _headers_mtime():
+            return obj
     extra = PATH_FLAGS if src.startswith(("bucket_", "batched", "adjoint", "mlp_")) else []
     cmd = [HIPCC, *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -41,10 +51,11 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, force: bool = True) -> str:
+    """Compile every source (force) or only those older than their inputs."""
     os.makedirs(BUILD, exist_ok=True)
     with ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 4)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+        objs = list(ex.map(lambda f: _compile(f, force), SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -57,4 +68,4 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, force="--changed" not in sys.argv)

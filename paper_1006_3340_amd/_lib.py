@@ -31,7 +31,7 @@ EXPORTS = ["lll_version", "lll_last_error", "lll_plan_create", "lll_plan_execute
            "lll_batch_execute", "lll_batch_results", "lll_batch_set_timing", "lll_batch_timing",
            "lll_batch_destroy", "lll_plan_greeks", "lll_plan_greeks_results", "lll_plan_greeks_vjp",
            "lll_plan_greeks_vjp_results", "lll_caplet_greeks", "lll_price_caplets_batched",
-           "lll_fp32_fma_peak",
+           "lll_fp32_fma_peak", "lll_price_caplets_static",
            "lll_mlp_create", "lll_mlp_destroy", "lll_mlp_params", "lll_mlp_generate",
            "lll_mlp_info", "lll_mlp_set_box", "lll_mlp_pairs", "lll_mlp_train", "lll_mlp_eval",
            "lll_plan_execute_mlp", "lll_plan_mlp_stats"]
@@ -89,6 +89,7 @@ def load():
     lib.lll_plan_destroy.argtypes = [vp]
     lib.lll_price_caplets.argtypes = [ctypes.POINTER(TermStructureC), i64, i32, u64, i32, dp, dp,
                                       dp, vp]
+    lib.lll_price_caplets_static.argtypes = lib.lll_price_caplets.argtypes
     dpp = ctypes.POINTER(dp)
     lib.lll_price_caplets_batched.argtypes = [ctypes.POINTER(TermStructureC), i32, i64, i32, u64,
                                               dpp, dpp, vp]
@@ -370,6 +371,20 @@ def price_caplets(ts, n_paths: int, scheme: int = FULL, seed: int = 1, precision
     _check(lib.lll_price_caplets(ctypes.byref(t.c), int(n_paths), int(scheme), int(seed),
                                  int(precision), _dp(price), _dp(se), _dp(mart),
                                  stream_handle(stream)))
+    return {"price": price, "stderr": se, "mart_resid": mart}
+
+
+def price_caplets_static(ts, n_paths: int, scheme: int = FULL, seed: int = 1,
+                         precision: int = FP32, stream=None) -> dict:
+    """lll_price_caplets_static: lll_price_caplets with every device buffer in
+    the library's static workspace (no device allocation)."""
+    lib = load()
+    t = _TS(ts)
+    N, S = ts.n_rates, ts.n_strikes
+    price = np.zeros((N, S)); se = np.zeros((N, S)); mart = np.zeros(N)
+    _check(lib.lll_price_caplets_static(ctypes.byref(t.c), int(n_paths), int(scheme), int(seed),
+                                        int(precision), _dp(price), _dp(se), _dp(mart),
+                                        stream_handle(stream)))
     return {"price": price, "stderr": se, "mart_resid": mart}
 
 

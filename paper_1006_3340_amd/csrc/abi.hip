@@ -44,6 +44,10 @@ bool finite_all(const double *a, size_t n) {
     return true;
 }
 
+}  // namespace
+
+namespace lll {
+
 // Input checks of paper Section 2: (LR2) positive forwards and a strictly
 // increasing tenor with matching accrual fractions; (LR1) bounded vols with
 // exponential moments -- for the NIG driver the drift integral is finite iff
@@ -106,6 +110,37 @@ int validate(const lll_term_structure *ts) {
     return LLL_OK;
 }
 
+// Scalar fields of a plan (sizes, bucket, driver, B(0, T_1)); the host copies
+// of the input arrays and the device buffers are set by the caller.
+void fill_plan_header(lll_plan &p, const lll_term_structure *ts, int precision, int64_t max_paths,
+                      int nmax) {
+    p.N = ts->n_rates;
+    p.s = ts->steps_per_period;
+    p.S = ts->n_strikes;
+    p.K = p.N * p.s;
+    p.driver = ts->driver;
+    p.precision = precision;
+    p.nmax = nmax > 0 ? nmax : bucket_for(p.N);
+    p.off = p.nmax - p.N;
+    p.struct_id = ts->struct_id;
+    p.product = ts->product;
+    p.B0_T1 = ts->B0_T1 > 0.0 ? ts->B0_T1 : 1.0 / (1.0 + ts->tenor[0] * ts->L0[0]);
+    p.alpha = ts->alpha;
+    p.beta = ts->beta;
+    p.delta_nig = ts->delta_nig;
+    p.c = ts->c;
+    p.max_paths = max_paths;
+    p.max_waves = (max_paths + kWaveSize - 1) / kWaveSize;
+    p.max_chunks = (p.max_waves + 255) / 256;
+    (void)hipGetDevice(&p.device);
+}
+
+}  // namespace lll
+
+namespace {
+
+using lll::validate;
+
 template <typename T>
 hipError_t dalloc(T **p, size_t n) {
     return hipMalloc(reinterpret_cast<void **>(p), n * sizeof(T) + 16);
@@ -150,30 +185,12 @@ int create_plan(const lll_term_structure *ts, int precision, int64_t max_paths, 
 
     lll_plan *p = new (std::nothrow) lll_plan();
     if (!p) return fail(LLL_ENOMEM, "host allocation failed");
-    p->N = ts->n_rates;
-    p->s = ts->steps_per_period;
-    p->S = ts->n_strikes;
-    p->K = p->N * p->s;
-    p->driver = ts->driver;
-    p->precision = precision;
-    p->nmax = nmax > 0 ? nmax : lll::bucket_for(p->N);
-    p->off = p->nmax - p->N;
-    p->struct_id = ts->struct_id;
-    p->product = ts->product;
-    p->B0_T1 = ts->B0_T1 > 0.0 ? ts->B0_T1 : 1.0 / (1.0 + ts->tenor[0] * ts->L0[0]);
-    p->alpha = ts->alpha;
-    p->beta = ts->beta;
-    p->delta_nig = ts->delta_nig;
-    p->c = ts->c;
-    p->max_paths = max_paths;
-    p->max_waves = (max_paths + lll::kWaveSize - 1) / lll::kWaveSize;
-    p->max_chunks = (p->max_waves + 255) / 256;
+    lll::fill_plan_header(*p, ts, precision, max_paths, nmax);
     p->tenor.assign(ts->tenor, ts->tenor + p->N);
     p->delta.assign(ts->delta, ts->delta + p->N);
     p->L0.assign(ts->L0, ts->L0 + p->N);
     p->vol.assign(ts->vol, ts->vol + (size_t)p->K * p->N);
     p->strikes.assign(ts->strikes, ts->strikes + (size_t)p->N * p->S);
-    (void)hipGetDevice(&p->device);
 
     const size_t esz = precision == LLL_FP64 ? sizeof(double) : sizeof(float);
     const size_t N = p->N, K = p->K, NM = p->nmax, S = p->S;

@@ -110,6 +110,11 @@ constexpr int kStatBase = 3;  // NSTAT = 3 S + 2
 // abi.hip: thread-local error text of the C ABI
 int fail(int code, const char *fmt, ...);
 int hip_fail(hipError_t e, const char *what);
+// abi.hip: host-side checks of a term structure (LLL_OK or a status with the
+// message set) and the scalar fields of a plan for it
+int validate(const lll_term_structure *ts);
+void fill_plan_header(lll_plan &p, const lll_term_structure *ts, int precision, int64_t max_paths,
+                      int nmax);
 
 // precompute.hip: first-order coefficients K2 (scheme LLL_FIRST_ORDER)
 hipError_t launch_first_order_tables(const lll_plan &p, hipStream_t st);

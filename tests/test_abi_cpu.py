@@ -123,3 +123,19 @@ def test_binding_constants_match_the_header():
     assert (L.N_MAX, L.N_MAX_MP, L.N_MAX_FP64, L.N_MAX_EXACT, L.S_MAX, L.Q) == (
         defines["N_MAX"], defines["N_MAX_MP"], defines["N_MAX_FP64"], defines["N_MAX_EXACT"],
         defines["S_MAX"], defines["Q"])
+
+
+def test_static_workspace_checks_on_the_host():
+    """lll_price_caplets_static rejects a pass larger than its static device
+    workspace, and the schemes it does not run, before any device call (so
+    this runs without a GPU)."""
+    import paper_1006_3340_amd as lll
+    with pytest.raises(lll.LLLError) as ei:
+        lll.price_caplets_static(workloads.learned_drift(), 1 << 20, lll.FULL)
+    assert ei.value.code == -1 and "static workspace holds" in str(ei.value)
+    with pytest.raises(lll.LLLError) as ei:
+        lll.price_caplets_static(workloads.plain_fp64(), 64, lll.PICARD_MP)
+    assert ei.value.code == -5
+    with pytest.raises(lll.LLLError) as ei:
+        lll.price_caplets_static(workloads.plain_fp64().copy(L0=-workloads.plain_fp64().L0), 64)
+    assert ei.value.code == -1
