@@ -77,6 +77,35 @@ def flops_per_path(ts, scheme: str) -> int:
     return sum(s * flops_per_path_step(scheme, N - m) for m in range(N))
 
 
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def stored_oracle_prices(fname: str, scheme: str, ts) -> dict:
+    """Prices of eq. (caplet) from the FP64 oracle's stored path sums (written
+    by tests/golden/make_oracle_sums.py from the oracle alone): chunk sums
+    added in order, delta_i B(0, T_*) sum p / n."""
+    import json
+    with open(os.path.join(GOLDEN, fname)) as f:
+        g = json.load(f)
+    sp = sum(np.asarray(c["sum_p"], dtype=np.float64) for c in g["schemes"][scheme])
+    itm = sum(np.asarray(c["n_itm"], dtype=np.float64) for c in g["schemes"][scheme])
+    B0T = ts.B0_T1 / np.prod(1.0 + ts.delta * ts.L0)
+    return {"price": ts.delta[:, None] * B0T * sp / g["n_paths"], "n_itm": itm,
+            "n_paths": g["n_paths"]}
+
+
+def per_caplet_error(price, ref: dict, ts, itm_floor: int = 100) -> dict:
+    """Error of each caplet-strike price against the oracle's: relative where
+    the oracle has >= itm_floor in-the-money paths, else absolute over the
+    at-the-money price of the same caplet (near-zero prices)."""
+    atm = int(np.argmin(np.abs(ts.strikes[0] / ts.L0[0] - 1.0)))
+    floored = ref["n_itm"] < itm_floor
+    den = np.where(floored, np.abs(ref["price"][:, atm:atm + 1]), np.abs(ref["price"]))
+    err = np.abs(price - ref["price"]) / den
+    return {"max": float(err.max()), "per_caplet_max": [float(v) for v in err.max(axis=1)],
+            "n_floored": int(floored.sum())}
+
+
 def cpu_baseline(ts, n_sample: int, schemes) -> dict:
     """The FP64 oracle, as it stands, on a bounded sample of the same workload."""
     import oracle
@@ -216,6 +245,18 @@ def bench_mlp(lll, stream, n: int = 1 << 20, train_steps: int = 3000) -> dict:
         for name in prices:
             rel = np.abs(prices[name][live] / prices["full"][live] - 1)
             out[name]["max_rel_err_vs_full"] = float(np.max(rel))
+        # the accuracy gate judged by the FP64 oracle's FULL prices (stored
+        # sums, 2^16 paths, same streams)
+        n16 = 1 << 16
+        ref = stored_oracle_prices("oracle_sums_mlp_n40_2p16.json", "full", ts)
+        gate = {}
+        for name, run in legs:
+            if name == "mlp":
+                plan.execute_mlp(net, True, n16, seed=1, stream=stream)
+            else:
+                plan.execute(lll.SCHEMES[name], n16, seed=1, stream=stream)
+            gate[name] = per_caplet_error(plan.results(stream)["price"], ref, ts)["max"]
+        out["vs_oracle_full_2p16"] = gate
         plan.execute_mlp(net, True, n, seed=1, judge_stride=8, stream=stream)
         st = plan.mlp_stats(stream)
         out["mlp"]["judge"] = {"stride": 8, "rate_steps": st["rate_steps"],
@@ -235,6 +276,23 @@ def bench_mlp(lll, stream, n: int = 1 << 20, train_steps: int = 3000) -> dict:
     for name in ("full", "picard", "first_order", "second_order"):
         fl = flops_per_path(ts, name) * n
         out[name]["frac_fp32_peak"] = fl / (out[name]["kernel_ms"] / 1e3) / PEAK_FP32
+    return out
+
+
+def bench_parity(lll, plan, ts, n, stream, schemes) -> dict:
+    """Prices of the timed launch configuration against the FP64 oracle on the
+    same Philox streams, per caplet (the oracle's sums at 2^20 paths are
+    stored: ~7 CPU-minutes), and each scheme against the oracle's FULL (the
+    metric's accuracy condition)."""
+    fname = "oracle_sums_gpu_n20_2p20.json"
+    out = {"reference": f"FP64 oracle, {fname}", "bar": 1e-4}
+    ref_full = stored_oracle_prices(fname, "full", ts)
+    for name in schemes:
+        plan.execute(lll.SCHEMES[name], n, seed=1, stream=stream)
+        price = plan.results(stream)["price"]
+        out[name] = per_caplet_error(price, stored_oracle_prices(fname, name, ts), ts)
+        if name != "full":
+            out[name]["vs_oracle_full"] = per_caplet_error(price, ref_full, ts)["max"]
     return out
 
 
@@ -436,6 +494,8 @@ def main(argv=None) -> int:
                     help="also time the pathwise Greeks pass (N=40, 2^20 paths)")
     ap.add_argument("--mlp", type=int, default=1,
                     help="also train the drift surrogate and time it (N=40, 2^20 paths)")
+    ap.add_argument("--mlp-train-steps", type=int, default=3000,
+                    help="Adam steps of the surrogate's training in the mlp leg")
     ap.add_argument("--mp", type=int, default=1,
                     help="also time the maturity-parallel PICARD layout (1) or not (0)")
     ap.add_argument("--kluge", type=int, default=1,
@@ -558,6 +618,8 @@ def main(argv=None) -> int:
         "host_io": {"call": "lll_price_caplets (one FULL pass, host buffers in and out)",
                     "ms": host_ms, "path_steps_per_s": n * ts.n_steps / (host_ms / 1e3)},
     }
+    if n == 1 << 20:
+        out["parity"] = bench_parity(lll, plan, ts, n, stream, schemes)
     out["reference_schemes"] = bench_reference_schemes(lll, plan, ts, n, stream)
     out["swaptions"] = bench_swaptions(lll, stream)
     if args.batched:
@@ -565,7 +627,7 @@ def main(argv=None) -> int:
     if args.adjoint:
         out["adjoint"] = bench_adjoint(lll, stream)
     if args.mlp:
-        out["mlp"] = bench_mlp(lll, stream)
+        out["mlp"] = bench_mlp(lll, stream, train_steps=args.mlp_train_steps)
     if args.mp:
         out["maturity_parallel"] = bench_maturity_parallel(lll, stream)
     if args.kluge:
