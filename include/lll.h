@@ -335,6 +335,35 @@ int lll_mlp_pairs(lll_mlp *mlp, const int64_t *pairs, int64_t n, float *state_ho
 int lll_mlp_train(lll_mlp *mlp, int n_steps, int batch, float lr, uint64_t seed, float *loss_host,
                   void *stream);
 
+/* Training on caller-owned pairs in device memory: feat_dev [n_pairs][96]
+ * bfloat16 bit patterns (the features of lll_mlp_generate's layout),
+ * label_dev [n_pairs] FP32 raw labels, divided by `sigma` (> 0) for the loss.
+ * Otherwise as lll_mlp_train: n_steps Adam steps (beta 0.9 / 0.999, eps 1e-8,
+ * bias correction with the network's step count t, which continues across
+ * calls and restarts when the parameters are set) at the learning rate
+ * lr (0.01 + 0.99 (1 + cos(pi j / n_steps)) / 2) of step j of the call, on
+ * minibatches of `batch` pairs drawn with replacement: draw i of step t is
+ * (w0 2^32 + w1) mod n_pairs for the Philox words of counter (t, i, 1, 2 << 24)
+ * and key seed.  loss_dev [n_steps] (FP32, may be NULL) receives the
+ * minibatch losses sum (y - label / sigma)^2 / (2 batch).  Asynchronous on
+ * `stream`: the inputs must stay valid until the stream reaches the end of
+ * the call; nothing is copied to the host.  The optimiser's buffers are
+ * allocated on first use (LLL_ENOMEM if that fails). */
+int lll_mlp_train_dev(lll_mlp *mlp, const uint16_t *feat_dev, const float *label_dev,
+                      int64_t n_pairs, float sigma, int n_steps, int batch, float lr, uint64_t seed,
+                      float *loss_dev, void *stream);
+
+/* Adam moments of the network after the work queued so far (waits for the
+ * device): m_host and v_host [LLL_MLP_PARAMS] FP32 (either may be NULL) and the
+ * step count t of the last step (step_host, may be NULL). */
+int lll_mlp_optimizer_state(lll_mlp *mlp, float *m_host, float *v_host, int64_t *step_host);
+
+/* Copy the pairs of the last lll_mlp_generate into caller device buffers on
+ * `stream` (asynchronous): feat_dev [n][96] bfloat16 bit patterns, label_dev [n]
+ * FP32, n = the pair count lll_mlp_info reports; LLL_EINVAL if capacity < n. */
+int lll_mlp_copy_pairs_dev(lll_mlp *mlp, uint16_t *feat_dev, float *label_dev, int64_t capacity,
+                           void *stream);
+
 /* Forward pass on n host feature rows [n][96] (rounded to BF16 on the device):
  * outputs y_host[n]; with targets (target_host[n]) also the gradient of
  * loss = sum (y - target)^2 / (2 n) with respect to the parameter vector

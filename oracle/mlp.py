@@ -206,3 +206,63 @@ def surrogate_paths(o, params, lo, hi, sigma, paths, use_net=True):
     sums = {"sum_p": sp, "sum_p2": sp2, "n_itm": itm, "sum_mart": mart, "sum_mart2": mart2,
             "n_paths": n, "fallbacks": fallbacks}
     return sums, Lfix, Dfix
+
+
+# ---------------------------------------------------------------------------
+# Training update (the surrogate's own optimiser; not part of the paper)
+# ---------------------------------------------------------------------------
+
+ADAM_B1, ADAM_B2, ADAM_EPS = 0.9, 0.999, 1e-8
+
+
+def adam_step(p, m, v, g, t, lr, b1=ADAM_B1, b2=ADAM_B2, eps=ADAM_EPS):
+    """One Adam step (Kingma & Ba 2015, Algorithm 1) at step t = 1, 2, ...:
+    exponential moving averages m, v of the gradient and of its square, their
+    bias corrections m / (1 - b1^t) and v / (1 - b2^t), and the parameter move
+    -lr m_hat / (sqrt(v_hat) + eps).  FP64; returns (p, m, v)."""
+    m = b1 * m + (1.0 - b1) * g
+    v = b2 * v + (1.0 - b2) * g * g
+    m_hat = m / (1.0 - b1 ** t)
+    v_hat = v / (1.0 - b2 ** t)
+    return p - lr * m_hat / (np.sqrt(v_hat) + eps), m, v
+
+
+def cosine_lr(lr, t, n_steps, floor=0.01):
+    """Learning rate of step t = 0 .. n_steps - 1 of a call: cosine decay from
+    lr towards floor * lr, lr (floor + (1 - floor) (1 + cos(pi t / n_steps)) / 2)."""
+    return lr * (floor + (1.0 - floor) * 0.5 * (1.0 + math.cos(math.pi * t / n_steps)))
+
+
+def minibatch(philox, seed, step, batch, n_pairs):
+    """Indices of the minibatch of Adam step `step` (1-based, counted over the
+    network's life): draw j takes the Philox-4x32-10 words of counter
+    (step, j, 1, 2 << 24) (tag 2 of the counter layout) under key (seed mod 2^32,
+    seed div 2^32) and returns (w0 2^32 + w1) mod n_pairs -- a draw with
+    replacement.  `philox(ctr, key)` is the oracle's generator."""
+    key = (seed & 0xFFFFFFFF, seed >> 32)
+    out = np.empty(batch, dtype=np.int64)
+    for j in range(batch):
+        w = philox((step & 0xFFFFFFFF, j, 1, 2 << 24), key)
+        out[j] = ((int(w[0]) << 32) | int(w[1])) % n_pairs
+    return out
+
+
+def train(p, feat, labels, sigma, n_steps, batch, lr, seed, philox, step0=0, m=None, v=None):
+    """The surrogate's training loop in FP64: per step t the minibatch of step
+    step0 + t + 1, the loss sum (y - label / sigma)^2 / (2 batch) and its
+    gradient through the network with the device's BF16 operand rounding
+    (``loss_and_grad(..., bf=True)``), and an Adam step at the cosine-decayed
+    learning rate.  Returns (p, m, v, losses)."""
+    p = np.asarray(p, dtype=np.float64).copy()
+    m = np.zeros_like(p) if m is None else np.asarray(m, dtype=np.float64).copy()
+    v = np.zeros_like(p) if v is None else np.asarray(v, dtype=np.float64).copy()
+    feat = np.asarray(feat, dtype=np.float64)
+    labels = np.asarray(labels, dtype=np.float64)
+    losses = []
+    for t in range(n_steps):
+        step = step0 + t + 1
+        idx = minibatch(philox, seed, step, batch, len(labels))
+        loss, g = loss_and_grad(p, feat[idx], labels[idx] / sigma, bf=True)
+        p, m, v = adam_step(p, m, v, g, step, cosine_lr(lr, t, n_steps))
+        losses.append(loss)
+    return p, m, v, np.array(losses)

@@ -34,7 +34,8 @@ EXPORTS = ["lll_version", "lll_last_error", "lll_plan_create", "lll_plan_execute
            "lll_fp32_fma_peak", "lll_price_caplets_static",
            "lll_mlp_create", "lll_mlp_destroy", "lll_mlp_params", "lll_mlp_generate",
            "lll_mlp_info", "lll_mlp_set_box", "lll_mlp_pairs", "lll_mlp_train", "lll_mlp_eval",
-           "lll_plan_execute_mlp", "lll_plan_mlp_stats"]
+           "lll_plan_execute_mlp", "lll_plan_mlp_stats", "lll_mlp_train_dev",
+           "lll_mlp_optimizer_state", "lll_mlp_copy_pairs_dev"]
 MLP_PARAMS, MLP_INPUTS = 14593, 96
 
 
@@ -110,6 +111,10 @@ def load():
     lib.lll_mlp_pairs.argtypes = [vp, i64p, i64, fp, i32p, i32p, fp, fp]
     lib.lll_mlp_train.argtypes = [vp, i32, i32, ctypes.c_float, u64, fp, vp]
     lib.lll_mlp_eval.argtypes = [vp, fp, fp, i64, fp, fp, fp, vp]
+    lib.lll_mlp_train_dev.argtypes = [vp, vp, vp, i64, ctypes.c_float, i32, i32, ctypes.c_float,
+                                      u64, vp, vp]
+    lib.lll_mlp_optimizer_state.argtypes = [vp, fp, fp, i64p]
+    lib.lll_mlp_copy_pairs_dev.argtypes = [vp, vp, vp, i64, vp]
     lib.lll_plan_execute_mlp.argtypes = [vp, vp, i32, i64, u64, i32, vp, vp]
     lib.lll_plan_mlp_stats.argtypes = [vp, dp, vp]
     lib.lll_plan_greeks.argtypes = [vp, i64, u64, vp]
@@ -489,6 +494,37 @@ class Mlp:
         _check(self.lib.lll_mlp_train(self.h, int(n_steps), int(batch), ctypes.c_float(lr),
                                       int(seed), _fp(loss), stream_handle(stream)))
         return loss
+
+    def train_dev(self, feat, labels, sigma: float, n_steps: int, batch: int = 16384,
+                  lr: float = 2e-3, seed: int = 1, loss=None, stream=None):
+        """lll_mlp_train_dev on device tensors: feat [n][96] bfloat16, labels [n]
+        float32, loss [n_steps] float32 (optional); asynchronous on `stream`."""
+        n = int(labels.shape[0])
+        assert tuple(feat.shape) == (n, MLP_INPUTS) and feat.element_size() == 2
+        assert labels.element_size() == 4
+        assert feat.is_contiguous() and labels.is_contiguous()
+        if loss is not None:
+            assert loss.numel() >= n_steps and loss.element_size() == 4 and loss.is_contiguous()
+        _check(self.lib.lll_mlp_train_dev(self.h, device_ptr(feat), device_ptr(labels), n,
+                                          ctypes.c_float(sigma), int(n_steps), int(batch),
+                                          ctypes.c_float(lr), int(seed), device_ptr(loss),
+                                          stream_handle(stream)))
+
+    def optimizer_state(self) -> dict:
+        m = np.zeros(MLP_PARAMS, dtype=np.float32)
+        v = np.zeros(MLP_PARAMS, dtype=np.float32)
+        t = ctypes.c_int64()
+        _check(self.lib.lll_mlp_optimizer_state(self.h, _fp(m), _fp(v), ctypes.byref(t)))
+        return {"m": m, "v": v, "step": t.value}
+
+    def copy_pairs_dev(self, feat, labels, stream=None):
+        """lll_mlp_copy_pairs_dev into device tensors feat [>=n][96] (2-byte
+        elements) and labels [>=n] float32."""
+        assert feat.element_size() == 2 and labels.element_size() == 4
+        assert feat.is_contiguous() and labels.is_contiguous() and feat.shape[-1] == MLP_INPUTS
+        _check(self.lib.lll_mlp_copy_pairs_dev(self.h, device_ptr(feat), device_ptr(labels),
+                                               min(int(feat.shape[0]), int(labels.shape[0])),
+                                               stream_handle(stream)))
 
     def eval(self, feat: np.ndarray, target: Optional[np.ndarray] = None, stream=None) -> dict:
         feat = np.ascontiguousarray(np.asarray(feat, dtype=np.float32))

@@ -327,6 +327,66 @@ int lll_mlp_train(lll_mlp *m, int n_steps, int batch, float lr, uint64_t seed, f
     return LLL_OK;
 }
 
+int lll_mlp_train_dev(lll_mlp *m, const uint16_t *feat_dev, const float *label_dev,
+                      int64_t n_pairs, float sigma, int n_steps, int batch, float lr, uint64_t seed,
+                      float *loss_dev, void *stream) {
+    if (!m || !feat_dev || !label_dev) return fail(LLL_EINVAL, "NULL argument");
+    if (n_pairs < 1 || n_pairs > ((int64_t)1 << 31) - 1)
+        return fail(LLL_EINVAL, "n_pairs=%lld outside 1..2^31-1", (long long)n_pairs);
+    if (!(sigma > 0.0f) || !std::isfinite(sigma)) return fail(LLL_EINVAL, "sigma must be > 0");
+    if (n_steps < 1 || n_steps > 1000000 || batch < 64 || batch > (1 << 20) || !(lr > 0.0f))
+        return fail(LLL_EINVAL, "bad training arguments");
+    int rc = ensure_train_scratch(m, batch, n_steps);
+    if (rc != LLL_OK) return rc;
+    hipStream_t st = as_stream(stream);
+    const __bf16 *feat = reinterpret_cast<const __bf16 *>(feat_dev);
+    float *loss = loss_dev ? loss_dev : m->loss;
+    hipError_t e = hipSuccess;
+    for (int t = 0; t < n_steps && e == hipSuccess; ++t) {
+        const double c = 0.5 * (1.0 + std::cos(3.141592653589793 * t / n_steps));
+        const float lr_t = static_cast<float>(lr * (0.01 + 0.99 * c));
+        const int64_t tt = ++m->adam_steps;
+        const float bc1 = static_cast<float>(1.0 / (1.0 - std::pow(0.9, (double)tt)));
+        const float bc2 = static_cast<float>(1.0 / (1.0 - std::pow(0.999, (double)tt)));
+        e = launch_batch_index(m->idx, batch, n_pairs, static_cast<uint32_t>(tt), seed, st);
+        if (e == hipSuccess)
+            e = launch_tiles(feat, label_dev, m->idx, batch, 1.0f / sigma, m->wts, m->wbf, m->gpart,
+                             m->lpart, nullptr, loss + t, m->wts, m->wbf, m->adam, nullptr, lr_t,
+                             bc1, bc2, st);
+    }
+    if (e != hipSuccess) return hip_fail(e, "training");
+    return LLL_OK;
+}
+
+int lll_mlp_optimizer_state(lll_mlp *m, float *m_host, float *v_host, int64_t *step_host) {
+    if (!m) return fail(LLL_EINVAL, "mlp is NULL");
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess && m_host)
+        e = hipMemcpy(m_host, m->adam, sizeof(float) * kParams, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && v_host)
+        e = hipMemcpy(v_host, m->adam + kParams, sizeof(float) * kParams, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "reading the optimiser state");
+    if (step_host) *step_host = m->adam_steps;
+    return LLL_OK;
+}
+
+int lll_mlp_copy_pairs_dev(lll_mlp *m, uint16_t *feat_dev, float *label_dev, int64_t capacity,
+                           void *stream) {
+    if (!m || !feat_dev || !label_dev) return fail(LLL_EINVAL, "NULL argument");
+    if (!m->have_data) return fail(LLL_EINVAL, "no training data generated");
+    if (capacity < m->n_pairs)
+        return fail(LLL_EINVAL, "capacity %lld < %lld pairs", (long long)capacity,
+                    (long long)m->n_pairs);
+    hipStream_t st = as_stream(stream);
+    hipError_t e = hipMemcpyAsync(feat_dev, m->feat, sizeof(__bf16) * m->n_pairs * kIn,
+                                  hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(label_dev, m->label, sizeof(float) * m->n_pairs, hipMemcpyDeviceToDevice,
+                           st);
+    if (e != hipSuccess) return hip_fail(e, "copying training pairs");
+    return LLL_OK;
+}
+
 int lll_mlp_eval(lll_mlp *m, const float *feat_host, const float *target_host, int64_t n,
                  float *y_host, float *grad_host, float *loss_host, void *stream) {
     if (!m || !feat_host) return fail(LLL_EINVAL, "NULL argument");

@@ -245,3 +245,137 @@ def test_surrogate_gain_over_first_order(gpu_lib, trained):
     assert stats["fallbacks"] <= 1e-3 * stats["rate_steps"]
     assert stats["judged"] > 0
     assert stats["judge_abs_err"] / stats["judge_abs_quad"] < 1e-4
+
+
+def test_surrogate_and_picard_against_oracle_full(gpu_lib, oracle_mod, trained):
+    """The metric's accuracy gate judged by the FP64 oracle: surrogate-drift
+    and Picard prices at 2^16 paths against the oracle's FULL prices on the
+    same streams (stored sums, tests/golden/oracle_sums_mlp_n40_2p16.json),
+    per caplet-strike, with the near-zero floor of the parity tests."""
+    from test_gpu_fullsize import C4_FILE, golden_sums, oracle_prices, per_caplet_errors, _table
+    ts, plan, net, _, _ = trained
+    n = 1 << 16
+    ref = oracle_prices(oracle_mod, ts, golden_sums(C4_FILE, "full"))
+    plan.execute_mlp(net, True, n, seed=1)
+    mlp = plan.results()
+    plan.execute_mlp(None, False, n, seed=1)
+    first = plan.results()
+    plan.execute(PICARD, n, seed=1)
+    pic = plan.results()
+    err = {}
+    for name, got in (("mlp", mlp), ("picard", pic), ("first_order", first)):
+        rel, floored = per_caplet_errors(got, ref, ts)
+        _table(f"mlp_n40 {name} 2^16 paths vs FP64 oracle FULL", rel, floored)
+        err[name] = float(rel.max())
+    print("max per-caplet error vs oracle FULL:", {k: f"{v:.2e}" for k, v in err.items()})
+    assert err["mlp"] <= 1e-4 and err["picard"] <= 1e-4
+    assert err["mlp"] < err["first_order"]
+
+
+def _kappa_np(u, ts):
+    g = math.sqrt(ts.alpha ** 2 - ts.beta ** 2)
+    return -ts.delta_nig * ts.beta / g * u + ts.delta_nig * (g - np.sqrt(ts.alpha ** 2 - (ts.beta + u) ** 2))
+
+
+def test_surrogate_drift_judged_against_fp64_quadrature(gpu_lib, oracle_mod, trained):
+    """The trained network's coupling C'_i + sigma net(features) against the
+    FP64 oracle's quadrature coupling at states drawn on the host: step k and
+    rate i uniform over the coupled (step, rate) pairs, log-rate states X_l
+    normal with the mean and variance of the driver-only dynamics
+    (-sum kappa(lambda) dt, sum lambda^2 Var(H_1) dt) up to t_k."""
+    ts, plan, net, _, _ = trained
+    o = oracle_mod.Oracle(ts)
+    info = net.info()
+    sigma = info["sigma"]
+    N, s = ts.n_rates, ts.steps_per_period
+    rng = np.random.default_rng(12)
+    g = math.sqrt(ts.alpha ** 2 - ts.beta ** 2)
+    var_h1 = ts.delta_nig * ts.alpha ** 2 / g ** 3
+    T = np.concatenate([[0.0], ts.tenor])
+    feats, labels, quads = [], [], []
+    for _ in range(400):
+        k = int(rng.integers(0, (N - 1) * s))
+        m = k // s
+        i = int(rng.integers(m, N - 1))
+        mean = -np.sum(_kappa_np(ts.vol[:k], ts) * o.dt[:k, None], axis=0)
+        var = np.sum(ts.vol[:k] ** 2 * o.dt[:k, None], axis=0) * var_h1
+        X = mean + np.sqrt(var) * rng.normal(size=N)
+        X[:m] = 0.0
+        L = ts.L0 * np.exp(X)
+        quad = -o.drift(k, L)[i] - o.kappa[k, i]
+        ell = ts.delta * L / (1 + ts.delta * L)
+        ell[:m] = 0.0
+        c1 = M.first_order_coupling(ell[None, :], ts.vol[k], ts)[0, i]
+        tk = T[m] + (k - m * s) * (T[m + 1] - T[m]) / s
+        feats.append(M.features(float(np.float32(tk / T[N])), X[None, :], i)[0])
+        labels.append(c1)
+        quads.append(quad)
+    y = net.eval(np.array(feats, dtype=np.float32))["y"].astype(np.float64)
+    C = np.array(labels) + sigma * y
+    q = np.array(quads)
+    rel = np.abs(C - q) / np.abs(q)
+    first = np.abs(np.array(labels) - q) / np.abs(q)
+    print(f"surrogate coupling vs FP64 quadrature at 400 host states: mean |err| / mean |C| "
+          f"{np.mean(np.abs(C - q)) / np.mean(np.abs(q)):.2e}, max rel {rel.max():.2e}; "
+          f"first-order alone: {np.mean(np.abs(np.array(labels) - q)) / np.mean(np.abs(q)):.2e}, "
+          f"max {first.max():.2e}")
+    # the coupling enters the drift times dt; ~1e-3 of it is ~1e-6 of the price
+    assert np.mean(np.abs(C - q)) / np.mean(np.abs(q)) < 1e-3
+    assert np.mean(np.abs(C - q)) < 0.1 * np.mean(np.abs(np.array(labels) - q))
+
+
+def test_training_update_matches_oracle(gpu_lib, oracle_mod):
+    """Three Adam steps of lll_mlp_train_dev on pairs made on the host, from
+    parameters set on the host, against the oracle's FP64 training loop (the
+    same minibatches from its own Philox, the loss and gradient with the
+    device's BF16 operand rounding, Adam with bias correction, the cosine
+    learning rate).  The device accumulates in FP32 and evaluates GELU with
+    hardware exp; a BF16 rounding flip moves one activation by 2^-8, so
+    gradients agree to ~1e-2 in norm and individual entries can differ where
+    the gradient is small.  Compared: the moments m, v per layer in norm, and
+    the parameter moves element by element where the oracle's gradient is
+    well above its own BF16-rounding sensitivity."""
+    import torch
+    rng = np.random.default_rng(21)
+    p0 = rng.normal(0.0, 1.0, M.N_PARAMS) / np.sqrt(np.repeat(
+        [96, 1, 64, 1, 64, 1, 64, 1], [6144, 64, 4096, 64, 4096, 64, 64, 1])) * 0.5
+    p0 = p0.astype(np.float32).astype(np.float64)
+    n_pairs, batch, steps, lr, seed, sigma = 3000, 256, 3, 1e-3, 5, 0.7
+    feat = M.bf16(np.concatenate([rng.uniform(0, 1, (n_pairs, 1)),
+                                  rng.normal(0, 0.3, (n_pairs, 40)),
+                                  np.eye(40)[rng.integers(0, 40, n_pairs)],
+                                  np.zeros((n_pairs, 15))], axis=1))
+    labels = (np.tanh(feat[:, 1] - 0.5 * feat[:, 3]) + 0.2 * feat[:, 0]).astype(np.float32)
+    with gpu_lib.Mlp(seed=1) as net:
+        net.set_params(p0.astype(np.float32))
+        fd = torch.tensor(feat.astype(np.float32)).to(torch.bfloat16).cuda()
+        ld = torch.tensor(labels, dtype=torch.float32).cuda()
+        loss_d = torch.zeros(steps, dtype=torch.float32, device="cuda")
+        net.train_dev(fd, ld, sigma, steps, batch=batch, lr=lr, seed=seed, loss=loss_d)
+        torch.cuda.synchronize()
+        p_gpu = net.params().astype(np.float64)
+        st = net.optimizer_state()
+    assert st["step"] == steps
+    p_ref, m_ref, v_ref, loss_ref = M.train(p0, feat, labels.astype(np.float64), sigma, steps,
+                                            batch, lr, seed, oracle_mod.philox4x32_10)
+    assert np.allclose(loss_d.cpu().numpy(), loss_ref, rtol=2e-3)
+    # sensitivity of the oracle's gradient to the BF16 rounding: the last
+    # step's gradient with and without the operand rounding
+    idx = M.minibatch(oracle_mod.philox4x32_10, seed, steps, batch, n_pairs)
+    _, g_bf = M.loss_and_grad(p_ref, feat[idx], labels[idx] / sigma, bf=True)
+    _, g_64 = M.loss_and_grad(p_ref, feat[idx], labels[idx] / sigma, bf=False)
+    offs = [0, 6144, 6208, 10304, 10368, 14464, 14528, 14592, 14593]
+    for a, b in zip(offs[:-1], offs[1:]):
+        for got, ref, tol in ((st["m"][a:b], m_ref[a:b], 2e-2), (st["v"][a:b], v_ref[a:b], 4e-2)):
+            err = np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-30)
+            assert err < tol, (a, b, err)
+    move_gpu, move_ref = p_gpu - p0, p_ref - p0
+    # every move is at most lr_t / (1 - b1^t) * |m_hat| / sqrt(v_hat) <= ~lr per step
+    assert np.all(np.abs(move_gpu) <= 3.5 * lr)
+    well = np.abs(g_bf) > 20.0 * np.abs(g_bf - g_64) + 1e-7
+    assert well.mean() > 0.5, well.mean()
+    bad = np.abs(move_gpu - move_ref) > 2e-2 * np.abs(move_ref) + 1e-9
+    assert np.mean(bad[well]) < 0.01, np.mean(bad[well])
+    # a plausible slip in the update (no bias correction, say) moves the first
+    # step by ~3x, far outside this agreement
+    assert np.median(np.abs(move_gpu[well] / move_ref[well] - 1.0)) < 1e-3

@@ -121,3 +121,71 @@ def test_surrogate_paths_first_order_close_to_full(oracle_mod):
     Lo, _ = o.paths(0, np.arange(4))
     d = np.abs(L0f / Lo - 1.0)
     assert 0 < d.max() < 1e-3
+
+
+def test_adam_step_and_cosine_schedule_match_torch():
+    """The oracle's Adam step and cosine learning-rate decay against
+    torch.optim.Adam with CosineAnnealingLR (eta_min = lr / 100), FP64, on a
+    sequence of gradients with a wide spread of magnitudes."""
+    import torch
+    rng = np.random.default_rng(4)
+    n, steps, lr = 300, 25, 2e-3
+    p0 = rng.normal(0, 1, n)
+    grads = [rng.normal(0, 1, n) * 10.0 ** rng.uniform(-9, 1, n) for _ in range(steps)]
+    w = torch.tensor(p0.copy(), dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([w], lr=lr, betas=(0.9, 0.999), eps=1e-8)
+    sched = torch.optim.lr_scheduler.CosineAnnealingLR(opt, T_max=steps, eta_min=lr / 100)
+    p, m, v = p0.copy(), np.zeros(n), np.zeros(n)
+    # torch forms the averages by lerp, m + (1 - b1)(g - m): the same value up
+    # to rounding relative to the magnitudes summed so far
+    g_abs, g_sq = np.zeros(n), np.zeros(n)
+    for t in range(steps):
+        g_abs += np.abs(grads[t])
+        g_sq += grads[t] ** 2
+        assert abs(M.cosine_lr(lr, t, steps) - opt.param_groups[0]["lr"]) <= 1e-15
+        w.grad = torch.tensor(grads[t], dtype=torch.float64)
+        opt.step()
+        sched.step()
+        p, m, v = M.adam_step(p, m, v, grads[t], t + 1, M.cosine_lr(lr, t, steps))
+        st = opt.state[w]
+        assert np.all(np.abs(st["exp_avg"].numpy() - m) <= 1e-14 * g_abs)
+        assert np.all(np.abs(st["exp_avg_sq"].numpy() - v) <= 1e-14 * g_sq)
+        assert np.all(np.abs(w.detach().numpy() - p) <= 1e-13 * (np.abs(p) + lr * (t + 1)))
+    # a plausible slip (no bias correction) is far outside that agreement
+    p1, _, _ = M.adam_step(p0, np.zeros(n), np.zeros(n), grads[0], 1, lr)
+    m_raw = 0.1 * grads[0]
+    p_nobc = p0 - lr * m_raw / (np.sqrt(0.001 * grads[0] ** 2) + 1e-8)
+    assert np.max(np.abs(p1 - p_nobc)) > lr
+
+
+def test_minibatch_draws_are_uniform_and_reproducible(oracle_mod):
+    """Minibatch indices from the oracle's Philox: in range, the same for the
+    same (seed, step), different across steps, and uniform (chi-square over 16
+    cells of 4096 draws)."""
+    a = M.minibatch(oracle_mod.philox4x32_10, 7, 3, 4096, 1000003)
+    assert np.array_equal(a, M.minibatch(oracle_mod.philox4x32_10, 7, 3, 4096, 1000003))
+    assert a.min() >= 0 and a.max() < 1000003
+    b = M.minibatch(oracle_mod.philox4x32_10, 7, 4, 4096, 1000003)
+    assert np.mean(a == b) < 0.01
+    counts = np.bincount(a * 16 // 1000003, minlength=16)
+    chi2 = np.sum((counts - 256.0) ** 2 / 256.0)
+    assert chi2 < 45.0          # 15 degrees of freedom: p ~ 1e-4
+
+
+def test_training_loop_reduces_loss_and_follows_the_gradient(oracle_mod):
+    """The oracle's training loop on a small regression: the loss falls, and
+    its first move is -lr g / (|g| + eps), i.e. -lr sign(g) wherever the
+    gradient is not tiny (after bias correction the first moments are g and g^2)."""
+    rng = np.random.default_rng(5)
+    p0 = _random_params(rng, 0.3)
+    feat = M.bf16(rng.normal(0, 0.5, (512, 96)))
+    labels = 3.0 * np.tanh(feat[:, 1] - feat[:, 2]) + 0.1
+    p1, m1, v1, l1 = M.train(p0, feat, labels, 2.0, 1, 128, 1e-3, 9, oracle_mod.philox4x32_10)
+    idx = M.minibatch(oracle_mod.philox4x32_10, 9, 1, 128, 512)
+    _, g = M.loss_and_grad(p0, feat[idx], labels[idx] / 2.0, bf=True)
+    assert np.allclose(p1 - p0, -1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-9, atol=1e-18)
+    big = np.abs(g) > 1e-4
+    assert np.allclose((p1 - p0)[big], -1e-3 * np.sign(g[big]), rtol=1e-4, atol=0)
+    assert np.allclose(m1, 0.1 * g) and np.allclose(v1, 0.001 * g * g)
+    _, _, _, losses = M.train(p0, feat, labels, 2.0, 60, 128, 3e-3, 9, oracle_mod.philox4x32_10)
+    assert losses[-10:].mean() < 0.5 * losses[:5].mean()
