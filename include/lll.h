@@ -109,7 +109,8 @@ typedef enum {
     LLL_FIRST_ORDER = 3,
     LLL_SECOND_ORDER = 4,
     LLL_PICARD_MP = 5,
-    LLL_EXACT = 6
+    LLL_EXACT = 6,
+    LLL_MLP_DRIFT = 7   /* FULL with the learned drift of an attached network (lll_plan_attach_mlp) */
 } lll_scheme;
 typedef enum { LLL_DRIVER_NIG = 0, LLL_DRIVER_BROWNIAN = 1 } lll_driver;
 typedef enum { LLL_FP32 = 0, LLL_FP64 = 1 } lll_precision;
@@ -139,6 +140,7 @@ typedef struct {
 /* Opaque plan: validated inputs copied to the device, precompute tables and
  * reduction buffers for up to max_paths paths.  Owned by the library. */
 typedef struct lll_plan lll_plan;
+typedef struct lll_mlp lll_mlp;  /* the drift surrogate (see below) */
 
 const char *lll_version(void);
 const char *lll_last_error(void);
@@ -177,6 +179,38 @@ int lll_plan_execute(lll_plan *plan, int scheme, int64_t n_paths, int64_t path_o
 int lll_plan_results(lll_plan *plan, double *price_host, double *stderr_host,
                      double *mart_resid_host, double *mart_se_host, double *n_itm_host,
                      void *stream);
+
+/* ---- device-resident inputs and outputs (asynchronous on `stream`) ---- */
+
+/* Replace the plan's initial forwards L(0, T_i) by L0_dev[N] (device FP64, or
+ * NULL to keep them) and shift each rate's vol curve in parallel by
+ * vol_shift_dev[N] (device FP64, or NULL): lambda(t_k, T_i) = the table the
+ * plan was created with + vol_shift_dev[i] (the "vol level" of rate i, paper
+ * Section 2's deterministic volatility lambda(., T_i)).  B(0, T_1), the
+ * strikes and the tenor stay as created.  Enqueued on `stream` (no host
+ * synchronisation): the inputs are read when the stream reaches the call and
+ * apply to every later execute or Greeks pass on the plan.  The host cannot
+ * check device values: the next pass checks them (positive finite forwards,
+ * finite vols and the moment condition of (LR1)) and, if they fail, its
+ * prices and Greeks are NaN and the host result calls return LLL_EINVAL or
+ * LLL_EMOMENT.  The first call with a shift copies the creation table to the
+ * device (allocation, synchronous). */
+int lll_plan_set_inputs_dev(lll_plan *plan, const double *L0_dev, const double *vol_shift_dev,
+                            void *stream);
+
+/* Copy the last execute's results into device buffers on `stream`
+ * (asynchronous): price_dev, stderr_dev [N][S], mart_resid_dev [N] (FP64; any
+ * may be NULL).  Non-finite values are not reported here (NaN prices mark
+ * invalid device inputs, see lll_plan_set_inputs_dev). */
+int lll_plan_results_dev(lll_plan *plan, double *price_dev, double *stderr_dev,
+                         double *mart_resid_dev, void *stream);
+
+/* Attach the surrogate network that scheme LLL_MLP_DRIFT of lll_plan_execute
+ * uses (NULL detaches); the network must outlive its use by the plan.
+ * LLL_MLP_DRIFT is lll_plan_execute_mlp with use_net = 1 and no judge, from
+ * path 0 (LLL_EUNSUPPORTED for path_offset != 0; LLL_EINVAL with no network).
+ * The one-shot calls have no network and reject the scheme. */
+int lll_plan_attach_mlp(lll_plan *plan, const lll_mlp *mlp);
 
 /* Raw per-caplet sums of the last execute, [N][LLL_NSTAT(S)] doubles:
  * sum p_j (S), sum p_j^2 (S), in-the-money counts (S), sum M, sum M^2 with
@@ -260,6 +294,23 @@ int lll_plan_greeks(lll_plan *plan, int64_t n_paths, uint64_t seed, void *stream
 int lll_plan_greeks_vjp(lll_plan *plan, int64_t n_paths, uint64_t seed, const double *weights_host,
                         void *stream);
 
+/* lll_plan_greeks_vjp with the weights in device memory (weights_dev[N] FP64,
+ * read when the stream reaches the call): no host synchronisation, for
+ * reverse-mode differentiation that stays on the device. */
+int lll_plan_greeks_vjp_dev(lll_plan *plan, int64_t n_paths, uint64_t seed,
+                            const double *weights_dev, void *stream);
+
+/* The last vector-Jacobian product into device buffers on `stream`
+ * (asynchronous): price_dev[N] (strike 0), vjp_L0_dev[N], vjp_vol_dev[N] (FP64;
+ * any may be NULL). */
+int lll_plan_greeks_vjp_results_dev(lll_plan *plan, double *price_dev, double *vjp_L0_dev,
+                                    double *vjp_vol_dev, void *stream);
+
+/* The last Greeks pass into device buffers on `stream` (asynchronous):
+ * price_dev[N], dP_dL0_dev[N][N], dP_dvol_dev[N][N] (FP64; any may be NULL). */
+int lll_plan_greeks_results_dev(lll_plan *plan, double *price_dev, double *dP_dL0_dev,
+                                double *dP_dvol_dev, void *stream);
+
 /* Results of the last lll_plan_greeks_vjp: price_host[N] (strike 0),
  * vjp_L0_host[N], vjp_vol_host[N]; waits for `stream`.  Any pointer may be NULL. */
 int lll_plan_greeks_vjp_results(lll_plan *plan, double *price_host, double *vjp_L0_host,
@@ -290,7 +341,6 @@ int lll_caplet_greeks(const lll_term_structure *ts, int64_t n_paths, uint64_t se
  * of 33..40 rates (the 40-slot register bucket), FP32, NIG driver. */
 #define LLL_MLP_PARAMS 14593
 #define LLL_MLP_INPUTS 96
-typedef struct lll_mlp lll_mlp;
 
 /* Allocate a network on the current device with Glorot-uniform weights drawn
  * from Philox (key = seed, counter word 3 = tag 2) and zero biases. */

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "liblll.so")
 LLL_OK = 0
 STATUS = {0: "LLL_OK", -1: "LLL_EINVAL", -2: "LLL_EMOMENT", -3: "LLL_ENOMEM", -4: "LLL_EHIP",
           -5: "LLL_EUNSUPPORTED", -6: "LLL_ENUMERIC"}
-FULL, PICARD, FROZEN, FIRST_ORDER, SECOND_ORDER, PICARD_MP, EXACT = 0, 1, 2, 3, 4, 5, 6
+FULL, PICARD, FROZEN, FIRST_ORDER, SECOND_ORDER, PICARD_MP, EXACT, MLP_DRIFT = 0, 1, 2, 3, 4, 5, 6, 7
 CAPLETS, SWAPTIONS = 0, 1
 FP32, FP64 = 0, 1
 N_MAX, N_MAX_MP, N_MAX_FP64, N_MAX_EXACT, S_MAX, Q = 40, 64, 24, 20, 8, 64
@@ -35,7 +35,9 @@ EXPORTS = ["lll_version", "lll_last_error", "lll_plan_create", "lll_plan_execute
            "lll_mlp_create", "lll_mlp_destroy", "lll_mlp_params", "lll_mlp_generate",
            "lll_mlp_info", "lll_mlp_set_box", "lll_mlp_pairs", "lll_mlp_train", "lll_mlp_eval",
            "lll_plan_execute_mlp", "lll_plan_mlp_stats", "lll_mlp_train_dev",
-           "lll_mlp_optimizer_state", "lll_mlp_copy_pairs_dev"]
+           "lll_mlp_optimizer_state", "lll_mlp_copy_pairs_dev", "lll_plan_set_inputs_dev",
+           "lll_plan_results_dev", "lll_plan_attach_mlp", "lll_plan_greeks_vjp_dev",
+           "lll_plan_greeks_vjp_results_dev", "lll_plan_greeks_results_dev"]
 MLP_PARAMS, MLP_INPUTS = 14593, 96
 
 
@@ -128,6 +130,12 @@ def load():
     lib.lll_batch_set_timing.argtypes = [vp, i32]
     lib.lll_batch_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_float)]
     lib.lll_batch_destroy.argtypes = [vp]
+    lib.lll_plan_set_inputs_dev.argtypes = [vp, vp, vp, vp]
+    lib.lll_plan_results_dev.argtypes = [vp, vp, vp, vp, vp]
+    lib.lll_plan_attach_mlp.argtypes = [vp, vp]
+    lib.lll_plan_greeks_vjp_dev.argtypes = [vp, i64, u64, vp, vp]
+    lib.lll_plan_greeks_vjp_results_dev.argtypes = [vp, vp, vp, vp, vp]
+    lib.lll_plan_greeks_results_dev.argtypes = [vp, vp, vp, vp, vp]
     lib.lll_plan_set_timing.argtypes = [vp, i32]
     lib.lll_plan_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_float)]
     for name in EXPORTS:
@@ -156,6 +164,18 @@ def stream_handle(stream) -> Optional[int]:
     if isinstance(stream, int):
         return stream
     return int(stream.cuda_stream)
+
+
+def dev_f64(t, n: int, name: str) -> Optional[int]:
+    """Address of a contiguous float64 device tensor with at least n elements
+    (None passes NULL); anything else raises before the library is called."""
+    if t is None:
+        return None
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+            and t.is_contiguous() and t.numel() >= n):
+        raise ValueError(f"{name}: needs a contiguous float64 CUDA tensor of >= {n} elements")
+    return int(t.data_ptr())
 
 
 def device_ptr(t) -> Optional[int]:
@@ -225,6 +245,46 @@ class Plan:
 
     def set_timing(self, enable: bool = True):
         _check(self.lib.lll_plan_set_timing(self.h, 1 if enable else 0))
+
+    def set_inputs_dev(self, L0=None, vol_shift=None, stream=None):
+        """lll_plan_set_inputs_dev: forwards L0 [N] and per-rate vol shifts [N]
+        from float64 device tensors (either may be None), asynchronous."""
+        _check(self.lib.lll_plan_set_inputs_dev(self.h, dev_f64(L0, self.N, "L0"),
+                                                dev_f64(vol_shift, self.N, "vol_shift"),
+                                                stream_handle(stream)))
+
+    def results_dev(self, price=None, stderr=None, mart_resid=None, stream=None):
+        """lll_plan_results_dev: the last execute's prices [N][S], standard
+        errors [N][S] and martingale residuals [N] into float64 device tensors."""
+        NS = self.N * self.S
+        _check(self.lib.lll_plan_results_dev(self.h, dev_f64(price, NS, "price"),
+                                             dev_f64(stderr, NS, "stderr"),
+                                             dev_f64(mart_resid, self.N, "mart_resid"),
+                                             stream_handle(stream)))
+
+    def attach_mlp(self, mlp):
+        """lll_plan_attach_mlp: the network scheme MLP_DRIFT uses (None detaches)."""
+        _check(self.lib.lll_plan_attach_mlp(self.h, mlp.h if mlp is not None else None))
+        self._mlp = mlp   # the network must outlive its use by the plan
+
+    def greeks_vjp_dev(self, n_paths: int, weights, seed: int = 1, stream=None):
+        """lll_plan_greeks_vjp_dev: weights [N] from a float64 device tensor."""
+        _check(self.lib.lll_plan_greeks_vjp_dev(self.h, int(n_paths), int(seed),
+                                                dev_f64(weights, self.N, "weights"),
+                                                stream_handle(stream)))
+        self.n_paths = int(n_paths)
+
+    def greeks_vjp_results_dev(self, price=None, vjp_L0=None, vjp_vol=None, stream=None):
+        N = self.N
+        _check(self.lib.lll_plan_greeks_vjp_results_dev(
+            self.h, dev_f64(price, N, "price"), dev_f64(vjp_L0, N, "vjp_L0"),
+            dev_f64(vjp_vol, N, "vjp_vol"), stream_handle(stream)))
+
+    def greeks_results_dev(self, price=None, dP_dL0=None, dP_dvol=None, stream=None):
+        N = self.N
+        _check(self.lib.lll_plan_greeks_results_dev(
+            self.h, dev_f64(price, N, "price"), dev_f64(dP_dL0, N * N, "dP_dL0"),
+            dev_f64(dP_dvol, N * N, "dP_dvol"), stream_handle(stream)))
 
     def timing(self) -> dict:
         """Durations (ms) of the last timed execute's stages, from HIP events."""

@@ -148,7 +148,7 @@ hipError_t dalloc(T **p, size_t n) {
 
 void free_tables(lll::DeviceTables &d) {
     void *ptrs[] = {d.tenor, d.delta, d.L0, d.vol, d.strikes, d.x, d.w, d.kappa, d.E, d.b0,
-                    d.steps, d.lam_pm, d.ew, d.lam, d.drift0, d.frozen, d.dt, d.cinv, d.k2, d.kex, d.L0s,
+                    d.steps, d.lam_pm, d.vol_base, d.ew, d.lam, d.drift0, d.frozen, d.dt, d.cinv, d.k2, d.kex, d.L0s,
                     d.deltas, d.partials, d.chunks, d.sums, d.results};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -156,6 +156,24 @@ void free_tables(lll::DeviceTables &d) {
 }
 
 hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Status of a pass whose results are not finite: the precompute's flags of
+// inputs set from device memory (non-finite or non-positive values, the
+// moment condition of (LR1)) or else non-finite payoffs.
+int nonfinite_status(lll_plan *plan, hipStream_t st) {
+    double flags[4] = {0, 0, 0, 0};
+    hipError_t e = hipMemcpyAsync(flags, plan->d.lam_pm, sizeof flags, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "reading input status");
+    if (flags[3] != 0.0)
+        return fail(LLL_EINVAL, "device inputs: a forward is not positive or a vol is not finite");
+    if (flags[2] != 0.0)
+        return fail(LLL_EMOMENT,
+                    "device inputs: exponential moments fail (Lambda+=%g vs alpha-beta=%g, "
+                    "Lambda-=%g vs alpha+beta=%g)",
+                    flags[0], plan->alpha - plan->beta, flags[1], plan->alpha + plan->beta);
+    return fail(LLL_ENUMERIC, "non-finite caplet price or standard error");
+}
 
 }  // namespace
 
@@ -202,7 +220,7 @@ int create_plan(const lll_term_structure *ts, int precision, int64_t max_paths, 
     };
     A(&d.tenor, N); A(&d.delta, N); A(&d.L0, N); A(&d.vol, K * N); A(&d.strikes, N * S);
     A(&d.x, lll::kQSize); A(&d.w, lll::kQSize); A(&d.kappa, K * N); A(&d.E, K * N * lll::kQSize);
-    A(&d.b0, K * N); A(&d.steps, 4 * N); A(&d.lam_pm, 2);
+    A(&d.b0, K * N); A(&d.steps, 4 * N); A(&d.lam_pm, 4);
     auto AB = [&](void **ptr, size_t n) {
         if (e == hipSuccess) e = hipMalloc(ptr, n * esz + 16);
     };
@@ -282,9 +300,23 @@ int lll_plan_destroy(lll_plan *plan) {
     return LLL_OK;
 }
 
+int lll_plan_attach_mlp(lll_plan *plan, const lll_mlp *mlp) {
+    if (!plan) return fail(LLL_EINVAL, "plan is NULL");
+    plan->mlp = mlp;
+    return LLL_OK;
+}
+
 int lll_plan_execute(lll_plan *plan, int scheme, int64_t n_paths, int64_t path_offset,
                      uint64_t seed, double *path_fix_dev, void *stream) {
     if (!plan) return fail(LLL_EINVAL, "plan is NULL");
+    if (scheme == LLL_MLP_DRIFT) {
+        if (!plan->mlp)
+            return fail(LLL_EINVAL, "LLL_MLP_DRIFT needs a network attached with lll_plan_attach_mlp");
+        if (path_offset != 0)
+            return fail(LLL_EUNSUPPORTED, "LLL_MLP_DRIFT runs paths from 0 (path_offset=%lld)",
+                        (long long)path_offset);
+        return lll_plan_execute_mlp(plan, plan->mlp, 1, n_paths, seed, 0, path_fix_dev, stream);
+    }
     if (scheme < LLL_FULL || scheme > LLL_EXACT)
         return fail(LLL_EINVAL, "unknown scheme %d", scheme);
     if (n_paths < 1 || n_paths > plan->max_paths)
@@ -367,8 +399,47 @@ int lll_plan_results(lll_plan *plan, double *price_host, double *stderr_host,
     if (n_itm_host) std::memcpy(n_itm_host, itm, N * S * sizeof(double));
     if (mart_resid_host) std::memcpy(mart_resid_host, mart, N * sizeof(double));
     if (mart_se_host) std::memcpy(mart_se_host, mse, N * sizeof(double));
-    if (!finite_all(price, N * S) || !finite_all(se, N * S))
-        return fail(LLL_ENUMERIC, "non-finite caplet price or standard error");
+    if (!finite_all(price, N * S) || !finite_all(se, N * S)) return nonfinite_status(plan, st);
+    return LLL_OK;
+}
+
+int lll_plan_set_inputs_dev(lll_plan *plan, const double *L0_dev, const double *vol_shift_dev,
+                            void *stream) {
+    if (!plan) return fail(LLL_EINVAL, "plan is NULL");
+    if (!L0_dev && !vol_shift_dev) return LLL_OK;
+    hipError_t e = hipSuccess;
+    if (vol_shift_dev && !plan->d.vol_base) {
+        // the curves are shifted from the table the plan was created with
+        const size_t bytes = (size_t)plan->K * plan->N * sizeof(double);
+        e = hipMalloc(&plan->d.vol_base, bytes);
+        if (e != hipSuccess) {
+            plan->d.vol_base = nullptr;
+            return fail(LLL_ENOMEM, "vol table copy: %s", hipGetErrorString(e));
+        }
+        e = hipMemcpy(plan->d.vol_base, plan->vol.data(), bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "copying the vol table");
+    }
+    e = lll::launch_set_inputs(*plan, L0_dev, vol_shift_dev, as_stream(stream));
+    if (e != hipSuccess) return hip_fail(e, "setting inputs");
+    return LLL_OK;
+}
+
+int lll_plan_results_dev(lll_plan *plan, double *price_dev, double *stderr_dev,
+                         double *mart_resid_dev, void *stream) {
+    if (!plan) return fail(LLL_EINVAL, "plan is NULL");
+    if (!plan->executed) return fail(LLL_EINVAL, "plan has not been executed");
+    const size_t N = plan->N, S = plan->S;
+    hipStream_t st = as_stream(stream);
+    const double *res = plan->d.results;
+    hipError_t e = hipSuccess;
+    auto D2D = [&](double *dst, const double *src, size_t n) {
+        if (dst && e == hipSuccess)
+            e = hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, st);
+    };
+    D2D(price_dev, res, N * S);
+    D2D(stderr_dev, res + N * S, N * S);
+    D2D(mart_resid_dev, res + 3 * N * S, N);
+    if (e != hipSuccess) return hip_fail(e, "copying results");
     return LLL_OK;
 }
 
@@ -713,8 +784,7 @@ int lll_plan_greeks_results(lll_plan *plan, double *price_host, double *dP_dL0_h
     if (dP_dL0_host) std::memcpy(dP_dL0_host, out.data(), N * N * sizeof(double));
     if (dP_dvol_host) std::memcpy(dP_dvol_host, out.data() + N * N, N * N * sizeof(double));
     if (price_host) std::memcpy(price_host, out.data() + 2 * N * N, N * sizeof(double));
-    if (!finite_all(out.data(), out.size()))
-        return fail(LLL_ENUMERIC, "non-finite Greeks");
+    if (!finite_all(out.data(), out.size())) return nonfinite_status(plan, st);
     return LLL_OK;
 }
 
@@ -729,7 +799,7 @@ int lll_plan_greeks_vjp(lll_plan *plan, int64_t n_paths, uint64_t seed, const do
     hipError_t e = hipSuccess;
     if (t) e = hipEventRecord(plan->ev[0], st);
     if (t && e == hipSuccess) e = hipEventRecord(plan->ev[1], st);
-    if (e == hipSuccess) e = lll::launch_greeks_vjp(*plan, n_paths, seed, weights_host, st);
+    if (e == hipSuccess) e = lll::launch_greeks_vjp(*plan, n_paths, seed, weights_host, nullptr, st);
     if (e != hipSuccess) return hip_fail(e, "adjoint launch");
     if (t) {
         e = hipEventRecord(plan->ev[2], st);
@@ -757,8 +827,67 @@ int lll_plan_greeks_vjp_results(lll_plan *plan, double *price_host, double *vjp_
     if (price_host) std::memcpy(price_host, out.data(), N * sizeof(double));
     if (vjp_L0_host) std::memcpy(vjp_L0_host, out.data() + N, N * sizeof(double));
     if (vjp_vol_host) std::memcpy(vjp_vol_host, out.data() + 2 * N, N * sizeof(double));
-    if (!finite_all(out.data(), out.size()))
-        return fail(LLL_ENUMERIC, "non-finite vector-Jacobian product");
+    if (!finite_all(out.data(), out.size())) return nonfinite_status(plan, st);
+    return LLL_OK;
+}
+
+int lll_plan_greeks_vjp_dev(lll_plan *plan, int64_t n_paths, uint64_t seed,
+                            const double *weights_dev, void *stream) {
+    if (!weights_dev) return fail(LLL_EINVAL, "weights are NULL");
+    const int rc = greeks_prepare(plan, n_paths);
+    if (rc != LLL_OK) return rc;
+    hipStream_t st = as_stream(stream);
+    const bool t = plan->timing;
+    hipError_t e = hipSuccess;
+    if (t) e = hipEventRecord(plan->ev[0], st);
+    if (t && e == hipSuccess) e = hipEventRecord(plan->ev[1], st);
+    if (e == hipSuccess) e = lll::launch_greeks_vjp(*plan, n_paths, seed, nullptr, weights_dev, st);
+    if (e != hipSuccess) return hip_fail(e, "adjoint launch");
+    if (t) {
+        e = hipEventRecord(plan->ev[2], st);
+        if (e == hipSuccess) e = hipEventRecord(plan->ev[3], st);
+        if (e != hipSuccess) return hip_fail(e, "recording timing events");
+    }
+    plan->timed = t;
+    plan->last_n_paths = n_paths;
+    plan->executed = true;
+    plan->vjp_done = true;
+    return LLL_OK;
+}
+
+int lll_plan_greeks_vjp_results_dev(lll_plan *plan, double *price_dev, double *vjp_L0_dev,
+                                    double *vjp_vol_dev, void *stream) {
+    if (!plan) return fail(LLL_EINVAL, "plan is NULL");
+    if (!plan->vjp_done) return fail(LLL_EINVAL, "no vector-Jacobian pass has run on this plan");
+    const size_t N = plan->N;
+    hipStream_t st = as_stream(stream);
+    hipError_t e = hipSuccess;
+    auto D2D = [&](double *dst, const double *src) {
+        if (dst && e == hipSuccess)
+            e = hipMemcpyAsync(dst, src, N * sizeof(double), hipMemcpyDeviceToDevice, st);
+    };
+    D2D(price_dev, plan->g.vjp_out);
+    D2D(vjp_L0_dev, plan->g.vjp_out + N);
+    D2D(vjp_vol_dev, plan->g.vjp_out + 2 * N);
+    if (e != hipSuccess) return hip_fail(e, "copying the vector-Jacobian product");
+    return LLL_OK;
+}
+
+int lll_plan_greeks_results_dev(lll_plan *plan, double *price_dev, double *dP_dL0_dev,
+                                double *dP_dvol_dev, void *stream) {
+    if (!plan) return fail(LLL_EINVAL, "plan is NULL");
+    if (!plan->greeks_done) return fail(LLL_EINVAL, "no Greeks pass has run on this plan");
+    const size_t N = plan->N;
+    hipStream_t st = as_stream(stream);
+    hipError_t e = hipSuccess;
+    auto D2D = [&](double *dst, const double *src, size_t n) {
+        if (dst && e == hipSuccess)
+            e = hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, st);
+    };
+    D2D(dP_dL0_dev, plan->g.out, N * N);
+    D2D(dP_dvol_dev, plan->g.out + N * N, N * N);
+    D2D(price_dev, plan->g.out + 2 * N * N, N);
+    if (e != hipSuccess) return hip_fail(e, "copying Greeks");
     return LLL_OK;
 }
 

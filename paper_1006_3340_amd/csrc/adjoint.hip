@@ -15,7 +15,7 @@ extern template hipError_t launch_adjoint_bucket<32>(const PathArgs<float> &, co
 extern template hipError_t launch_adjoint_bucket<40>(const PathArgs<float> &, const AdjArgs &, hipStream_t);
 #define LLL_VJP_EXTERN(NM)                                                                         \
     extern template hipError_t launch_vjp_bucket<NM>(const PathArgs<float> &, const AdjArgs &,    \
-                                                     const VjpArgs &, const float *, hipStream_t);
+                                                     const VjpArgs &, hipStream_t);
 LLL_VJP_EXTERN(8)
 LLL_VJP_EXTERN(16)
 LLL_VJP_EXTERN(24)
@@ -68,7 +68,8 @@ __global__ void __launch_bounds__(64) setup_adjoint_tables_kernel(
 __global__ void __launch_bounds__(64) greeks_finalize_kernel(
     const double *__restrict__ gsums, const double *__restrict__ results,
     const double *__restrict__ delta, const double *__restrict__ L0, int N, int S, double B0_T1,
-    int64_t n_paths, int product, double *__restrict__ out) {
+    int64_t n_paths, int product, const double *__restrict__ status, double *__restrict__ out) {
+    const double poison = (status[2] != 0.0 || status[3] != 0.0) ? __builtin_nan("") : 0.0;
     double prod_all = 1.0;
     for (int l = 0; l < N; ++l) prod_all *= 1.0 + delta[l] * L0[l];
     const double B0T = B0_T1 / prod_all;
@@ -79,8 +80,9 @@ __global__ void __launch_bounds__(64) greeks_finalize_kernel(
         price[i] = P;
         const double scale = (product == LLL_SWAPTIONS ? 1.0 : delta[i]) * B0T / n;
         for (int l = 0; l < N; ++l) {
-            dL[i * N + l] = scale * gsums[(size_t)i * 2 * N + l] - P * delta[l] / (1.0 + delta[l] * L0[l]);
-            dV[i * N + l] = scale * gsums[(size_t)i * 2 * N + N + l];
+            dL[i * N + l] =
+                scale * gsums[(size_t)i * 2 * N + l] - P * delta[l] / (1.0 + delta[l] * L0[l]) + poison;
+            dV[i * N + l] = scale * gsums[(size_t)i * 2 * N + N + l] + poison;
         }
     }
 }
@@ -93,20 +95,35 @@ struct VjpWeights {
     double g[LLL_N_MAX];
 };
 
+// The weights g of a vector-Jacobian product (host values passed by value,
+// or device memory) and the FP32 seeds g_i s_i of the reverse sweep.
+__global__ void __launch_bounds__(64) vjp_weights_kernel(VjpWeights host, const double *__restrict__ dev,
+                                                         const double *__restrict__ delta, int N,
+                                                         int product, double *__restrict__ g_out,
+                                                         float *__restrict__ w_out) {
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        const double g = dev ? dev[i] : host.g[i];
+        g_out[i] = g;
+        w_out[i] = static_cast<float>(g * (product == LLL_SWAPTIONS ? 1.0 : delta[i]));
+    }
+}
+
 __global__ void __launch_bounds__(64) vjp_finalize_kernel(
     const double *__restrict__ vsums, const double *__restrict__ results,
-    const double *__restrict__ delta, const double *__restrict__ L0, VjpWeights wts, int N, int S,
-    double B0_T1, int64_t n_paths, double *__restrict__ out) {
+    const double *__restrict__ delta, const double *__restrict__ L0, const double *__restrict__ wg,
+    int N, int S, double B0_T1, int64_t n_paths, const double *__restrict__ status,
+    double *__restrict__ out) {
+    const double poison = (status[2] != 0.0 || status[3] != 0.0) ? __builtin_nan("") : 0.0;
     double prod_all = 1.0, gP = 0.0;
     for (int l = 0; l < N; ++l) {
         prod_all *= 1.0 + delta[l] * L0[l];
-        gP += wts.g[l] * results[l * S];
+        gP += wg[l] * results[l * S];
     }
     const double scale = B0_T1 / prod_all / static_cast<double>(n_paths);
     for (int l = threadIdx.x; l < N; l += blockDim.x) {
         out[l] = results[l * S];
-        out[N + l] = scale * vsums[l] - gP * delta[l] / (1.0 + delta[l] * L0[l]);
-        out[2 * N + l] = scale * vsums[N + l];
+        out[N + l] = scale * vsums[l] - gP * delta[l] / (1.0 + delta[l] * L0[l]) + poison;
+        out[2 * N + l] = scale * vsums[N + l] + poison;
     }
 }
 
@@ -153,13 +170,15 @@ hipError_t greeks_alloc(lll_plan &p) {
     A((void **)&g.out, (2 * N * N + N) * sizeof(double));
     A((void **)&g.vjp_xb, N * P * sizeof(float));
     A((void **)&g.vjp_out, 3 * N * sizeof(double));
+    A((void **)&g.vjp_g, N * sizeof(double));
+    A((void **)&g.vjp_w, N * sizeof(float));
     return e;
 }
 
 void greeks_free(lll_plan &p) {
     GreeksBuffers &g = p.g;
     void *ptrs[] = {g.xe, g.dkap, g.w32, g.inv_L0, g.ckpt, g.fix, g.scr, g.scr_dh, g.gpart,
-                    g.gchunks, g.gsums, g.out, g.vjp_xb, g.vjp_out};
+                    g.gchunks, g.gsums, g.out, g.vjp_xb, g.vjp_out, g.vjp_g, g.vjp_w};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     p.g = GreeksBuffers{};
@@ -209,7 +228,7 @@ hipError_t reduce_cols(const double *in, int64_t rows, int cols, double *chunks_
 }  // namespace
 
 hipError_t launch_greeks_vjp(const lll_plan &p, int64_t n_paths, uint64_t seed,
-                             const double *weights, hipStream_t st) {
+                             const double *weights_host, const double *weights_dev, hipStream_t st) {
     using namespace adj;
     const GreeksBuffers &gb = p.g;
     AdjArgs g;
@@ -222,21 +241,23 @@ hipError_t launch_greeks_vjp(const lll_plan &p, int64_t n_paths, uint64_t seed,
                        st, gb.gpart, n_part);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
+    VjpWeights wts{};
+    if (weights_host)
+        for (int i = 0; i < p.N; ++i) wts.g[i] = weights_host[i];
+    hipLaunchKernelGGL(vjp_weights_kernel, dim3(1), dim3(64), 0, st, wts, weights_dev, p.d.delta,
+                       p.N, p.product, gb.vjp_g, gb.vjp_w);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
     VjpArgs v;
     v.xb = gb.vjp_xb;
     v.part = gb.gpart;
-    VjpWeights wts{};
-    float w[LLL_N_MAX];
-    for (int i = 0; i < p.N; ++i) {
-        wts.g[i] = weights[i];
-        w[i] = static_cast<float>(weights[i] * (p.product == LLL_SWAPTIONS ? 1.0 : p.delta[i]));
-    }
+    v.w = detail::as_const<float>(gb.vjp_w);
     switch (p.nmax) {
-        case 8: e = launch_vjp_bucket<8>(a, g, v, w, st); break;
-        case 16: e = launch_vjp_bucket<16>(a, g, v, w, st); break;
-        case 24: e = launch_vjp_bucket<24>(a, g, v, w, st); break;
-        case 32: e = launch_vjp_bucket<32>(a, g, v, w, st); break;
-        case 40: e = launch_vjp_bucket<40>(a, g, v, w, st); break;
+        case 8: e = launch_vjp_bucket<8>(a, g, v, st); break;
+        case 16: e = launch_vjp_bucket<16>(a, g, v, st); break;
+        case 24: e = launch_vjp_bucket<24>(a, g, v, st); break;
+        case 32: e = launch_vjp_bucket<32>(a, g, v, st); break;
+        case 40: e = launch_vjp_bucket<40>(a, g, v, st); break;
         default: return hipErrorInvalidValue;
     }
     if (e != hipSuccess) return e;
@@ -245,7 +266,8 @@ hipError_t launch_greeks_vjp(const lll_plan &p, int64_t n_paths, uint64_t seed,
     e = reduce_cols(gb.gpart, waves, 2 * p.N, gb.gchunks, gb.gsums, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(vjp_finalize_kernel, dim3(1), dim3(64), 0, st, gb.gsums, p.d.results,
-                       p.d.delta, p.d.L0, wts, p.N, p.S, p.B0_T1, n_paths, gb.vjp_out);
+                       p.d.delta, p.d.L0, gb.vjp_g, p.N, p.S, p.B0_T1, n_paths, p.d.lam_pm,
+                       gb.vjp_out);
     return hipGetLastError();
 }
 
@@ -272,7 +294,7 @@ hipError_t launch_greeks(const lll_plan &p, int64_t n_paths, uint64_t seed, hipS
     e = reduce_cols(gb.gpart, waves, p.N * 2 * p.N, gb.gchunks, gb.gsums, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(greeks_finalize_kernel, dim3(1), dim3(64), 0, st, gb.gsums, d.results,
-                       d.delta, d.L0, p.N, p.S, p.B0_T1, n_paths, p.product, gb.out);
+                       d.delta, d.L0, p.N, p.S, p.B0_T1, n_paths, p.product, d.lam_pm, gb.out);
     return hipGetLastError();
 }
 

@@ -6,6 +6,6 @@ namespace lll {
 namespace adj {
 template hipError_t launch_adjoint_bucket<40>(const PathArgs<float> &, const AdjArgs &, hipStream_t);
 template hipError_t launch_vjp_bucket<40>(const PathArgs<float> &, const AdjArgs &, const VjpArgs &,
-                                           const float *, hipStream_t);
+                                           hipStream_t);
 }  // namespace adj
 }  // namespace lll

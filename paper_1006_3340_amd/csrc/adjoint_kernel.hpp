@@ -365,14 +365,16 @@ __device__ __forceinline__ void sweep(const PathArgs<float> &a, const AdjArgs &g
 struct VjpArgs {
     float *xb;      // [N][n_paths] state adjoint by rate, carried between periods
     double *part;   // [waves][2N] sums of L0bar (first N) and vbar
+    detail::cptr<float> w;  // [N] seeds g_m s_m of the products (device memory)
 };
 
 template <int NMAX, int JC>
 __device__ __forceinline__ void vjp_period(const PathArgs<float> &a, const AdjArgs &g,
-                                           const VjpArgs &v, float w, int64_t gid, bool active,
+                                           const VjpArgs &v, int64_t gid, bool active,
                                            float *__restrict__ accL0, float *__restrict__ accV) {
     const int lane = threadIdx.x;
     const int m = JC - a.off;
+    const float w = v.w[m];
     const int N = a.N;
     const int64_t p = a.path_offset + gid;
     const uint32_t p_lo = static_cast<uint32_t>(p);
@@ -431,13 +433,13 @@ __global__ void __launch_bounds__(kAdjBlock) sweep_kernel(PathArgs<float> a, Adj
 
 template <int NMAX, int JC>
 __global__ void __launch_bounds__(kAdjBlock) vjp_period_kernel(PathArgs<float> a, AdjArgs g,
-                                                               VjpArgs v, float w) {
+                                                               VjpArgs v) {
     __shared__ float accL0[(NMAX - JC) * kAdjBlock];
     __shared__ float accV[(NMAX - JC) * kAdjBlock];
     const int64_t gid = static_cast<int64_t>(blockIdx.x) * kAdjBlock + threadIdx.x;
     const int64_t wave_first = gid - threadIdx.x;
     if (wave_first >= a.n_paths) return;
-    vjp_period<NMAX, JC>(a, g, v, w, gid, gid < a.n_paths, accL0, accV);
+    vjp_period<NMAX, JC>(a, g, v, gid, gid < a.n_paths, accL0, accV);
 }
 
 template <int NMAX, int PRODUCT>
@@ -464,16 +466,16 @@ hipError_t launch_sweep(std::integer_sequence<int, Js...>, int jc, dim3 grid,
 
 template <int NMAX, int JC>
 hipError_t launch_one_vjp(dim3 grid, const PathArgs<float> &a, const AdjArgs &g, const VjpArgs &v,
-                          float w, hipStream_t st) {
-    hipLaunchKernelGGL((vjp_period_kernel<NMAX, JC>), grid, dim3(kAdjBlock), 0, st, a, g, v, w);
+                          hipStream_t st) {
+    hipLaunchKernelGGL((vjp_period_kernel<NMAX, JC>), grid, dim3(kAdjBlock), 0, st, a, g, v);
     return hipGetLastError();
 }
 
 template <int NMAX, int... Js>
 hipError_t launch_vjp(std::integer_sequence<int, Js...>, int jc, dim3 grid, const PathArgs<float> &a,
-                      const AdjArgs &g, const VjpArgs &v, float w, hipStream_t st) {
+                      const AdjArgs &g, const VjpArgs &v, hipStream_t st) {
     hipError_t e = hipErrorInvalidValue;
-    (void)((jc == Js ? (e = launch_one_vjp<NMAX, Js>(grid, a, g, v, w, st), 0) : 0) + ...);
+    (void)((jc == Js ? (e = launch_one_vjp<NMAX, Js>(grid, a, g, v, st), 0) : 0) + ...);
     return e;
 }
 
@@ -506,15 +508,14 @@ hipError_t launch_forward(dim3 grid, const PathArgs<float> &a, const AdjArgs &g,
 }
 
 // Forward pass with checkpoints, then the periods from the last to the first
-// (w[m] = weight of caplet m times delta_m; v.part must be zero).
+// (v.w[m] = weight of product m times its price scale; v.part must be zero).
 template <int NMAX>
 hipError_t launch_vjp_bucket(const PathArgs<float> &a, const AdjArgs &g, const VjpArgs &v,
-                             const float *w, hipStream_t st) {
+                             hipStream_t st) {
     const dim3 grid(static_cast<unsigned>((a.n_paths + kAdjBlock - 1) / kAdjBlock));
     hipError_t e = launch_forward<NMAX>(grid, a, g, st);
     for (int m = a.N - 1; m >= 0 && e == hipSuccess; --m)
-        e = launch_vjp<NMAX>(std::make_integer_sequence<int, NMAX>{}, a.off + m, grid, a, g, v, w[m],
-                             st);
+        e = launch_vjp<NMAX>(std::make_integer_sequence<int, NMAX>{}, a.off + m, grid, a, g, v, st);
     return e;
 }
 

@@ -28,7 +28,8 @@ struct DeviceTables {
     double *E = nullptr;                        // [K][N][Q]
     double *b0 = nullptr;                       // [K][N]
     double *steps = nullptr;                    // [N][4] per-period increment constants
-    double *lam_pm = nullptr;                   // [2] Lambda_+, Lambda_-
+    double *lam_pm = nullptr;                   // [4] Lambda_+, Lambda_-, moment flag, input flag
+    double *vol_base = nullptr;                 // [K][N] the creation vol table (first shifted input)
     // path-kernel layout in the plan's precision (slot columns, nmax wide)
     void *ew = nullptr;        // [K][Q][nmax][2]  (E, W E)
     void *lam = nullptr;       // [K][nmax]
@@ -67,6 +68,8 @@ struct GreeksBuffers {
     float *ckpt = nullptr, *fix = nullptr, *scr = nullptr, *scr_dh = nullptr;
     double *gpart = nullptr, *gchunks = nullptr, *gsums = nullptr, *out = nullptr;
     float *vjp_xb = nullptr;   // [N][paths] state adjoint carried between periods
+    double *vjp_g = nullptr;   // [N] the weights g of the vector-Jacobian product
+    float *vjp_w = nullptr;    // [N] g_i times the product's price scale (delta_i or 1)
     double *vjp_out = nullptr; // [3N] price, sum_i g_i dP_i/dL0, sum_i g_i dP_i/dvol
 };
 }  // namespace lll
@@ -84,6 +87,7 @@ struct lll_plan {
     lll::GreeksBuffers g;
     lll::MlpBuffers mb;
     int64_t last_n_paths = 0, greeks_n_paths = 0;
+    const lll_mlp *mlp = nullptr;  // network of scheme LLL_MLP_DRIFT (lll_plan_attach_mlp)
     bool mlp_done = false;
     bool greeks_done = false;
     bool vjp_done = false;
@@ -124,7 +128,7 @@ hipError_t greeks_alloc(lll_plan &p);
 void greeks_free(lll_plan &p);
 hipError_t launch_greeks(const lll_plan &p, int64_t n_paths, uint64_t seed, hipStream_t st);
 hipError_t launch_greeks_vjp(const lll_plan &p, int64_t n_paths, uint64_t seed,
-                             const double *weights, hipStream_t st);
+                             const double *weights_host, const double *weights_dev, hipStream_t st);
 
 // mlp_host.hip
 void mlp_plan_free(lll_plan &p);
@@ -137,6 +141,10 @@ hipError_t launch_batched(const lll_batch &b, int scheme, hipStream_t st);
 
 // precompute.hip
 hipError_t launch_precompute(const lll_plan &p, hipStream_t st);
+// precompute.hip: replace the initial forwards (L0_dev [N], or NULL) and shift
+// each rate's vol curve from the creation table (shift_dev [N], or NULL)
+hipError_t launch_set_inputs(const lll_plan &p, const double *L0_dev, const double *shift_dev,
+                             hipStream_t st);
 
 // picard_mp.hip: PICARD in the maturity-parallel layout; its buffers hold at
 // most kMpBufferBytes, so larger runs go in chunks of picard_mp_chunk paths

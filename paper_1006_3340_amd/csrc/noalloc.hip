@@ -79,7 +79,7 @@ size_t carve(lll_plan &p, unsigned char *base, int64_t n_paths, bool first_order
     DeviceTables &d = p.d;
     D(&d.tenor, N); D(&d.delta, N); D(&d.L0, N); D(&d.vol, K * N); D(&d.strikes, N * S);
     D(&d.x, Q); D(&d.w, Q); D(&d.kappa, K * N); D(&d.E, K * N * Q); D(&d.b0, K * N);
-    D(&d.steps, 4 * N); D(&d.lam_pm, 2);
+    D(&d.steps, 4 * N); D(&d.lam_pm, 4);
     R(&d.ew, K * Q * NM * 2); R(&d.lam, K * NM); R(&d.drift0, K * NM); R(&d.frozen, K * NM);
     R(&d.dt, K); R(&d.cinv, NM);
     if (first_order) R(&d.k2, K * NM * NM);
@@ -104,7 +104,9 @@ extern "C" int lll_price_caplets_static(const lll_term_structure *ts, int64_t n_
     if (precision != LLL_FP32 && precision != LLL_FP64)
         return fail(LLL_EINVAL, "unknown precision %d", precision);
     if (scheme < LLL_FULL || scheme > LLL_SECOND_ORDER)
-        return fail(scheme == LLL_PICARD_MP || scheme == LLL_EXACT ? LLL_EUNSUPPORTED : LLL_EINVAL,
+        return fail(scheme == LLL_PICARD_MP || scheme == LLL_EXACT || scheme == LLL_MLP_DRIFT
+                        ? LLL_EUNSUPPORTED
+                        : LLL_EINVAL,
                     "scheme %d: the static workspace runs FULL, PICARD, FROZEN, FIRST_ORDER and "
                     "SECOND_ORDER",
                     scheme);

@@ -85,8 +85,11 @@ __global__ void __launch_bounds__(64) finalize_kernel(const double *__restrict__
                                                       const double *__restrict__ delta,
                                                       const double *__restrict__ L0, int N, int S,
                                                       double B0_T1, int64_t n_paths, int product,
+                                                      const double *__restrict__ status,
                                                       double *__restrict__ res) {
     const int nstat = 3 * S + 2;
+    // inputs set from device memory that fail the checks of Section 2 give NaN
+    const double poison = (status[2] != 0.0 || status[3] != 0.0) ? __builtin_nan("") : 0.0;
     double prod_all = 1.0;
     for (int l = 0; l < N; ++l) prod_all *= 1.0 + delta[l] * L0[l];
     const double B0T = B0_T1 / prod_all;
@@ -101,8 +104,8 @@ __global__ void __launch_bounds__(64) finalize_kernel(const double *__restrict__
         for (int t = 0; t < S; ++t) {
             const double mean = sr[t] / n;
             const double var = fmax(sr[S + t] / n - mean * mean, 0.0);
-            price[r * S + t] = scale * mean;
-            se[r * S + t] = scale * sqrt(var / nm1);
+            price[r * S + t] = scale * mean + poison;
+            se[r * S + t] = scale * sqrt(var / nm1) + poison;
             itm[r * S + t] = sr[2 * S + t];
         }
         double fwd = 1.0;
@@ -180,7 +183,7 @@ hipError_t launch_reduce(const lll_plan &p, int64_t n_paths, hipStream_t st) {
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(64), 0, st, p.d.sums, p.d.delta, p.d.L0, p.N,
-                       p.S, p.B0_T1, n_paths, p.product, p.d.results);
+                       p.S, p.B0_T1, n_paths, p.product, p.d.lam_pm, p.d.results);
     return hipGetLastError();
 }
 

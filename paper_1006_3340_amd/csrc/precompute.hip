@@ -43,17 +43,21 @@ __global__ void __launch_bounds__(64) setup_rule_kernel(
     const int t = threadIdx.x;
     const int K = N * s;
     double lp = 0.0, lm = 0.0;
+    int bad = 0;  // inputs the host could not check (set from device memory)
     for (int k = t; k < K; k += 64) {
         const int m = k / s;
         double sp = 0.0, sm = 0.0;
         for (int r = m; r < N; ++r) {
             const double v = vol[(size_t)k * N + r];
+            bad |= !isfinite(v);
             sp += fmax(v, 0.0);
             sm += fmax(-v, 0.0);
         }
         lp = fmax(lp, sp);
         lm = fmax(lm, sm);
     }
+    for (int r = t; r < N; r += 64) bad |= !(L0[r] > 0.0) || !isfinite(L0[r]);
+    bad = __syncthreads_or(bad);
     red_p[t] = lp;
     red_m[t] = lm;
     __syncthreads();
@@ -68,6 +72,10 @@ __global__ void __launch_bounds__(64) setup_rule_kernel(
     if (t == 0) {
         lam_pm[0] = Lp;
         lam_pm[1] = Lm;
+        // (LR1): the drift integral is finite iff Lambda_+ < alpha - beta and
+        // Lambda_- < alpha + beta; the pricing pass returns NaN otherwise
+        lam_pm[2] = (driver == kNig && !(Lp < alpha - beta && Lm < alpha + beta)) ? 1.0 : 0.0;
+        lam_pm[3] = bad ? 1.0 : 0.0;
     }
     if (driver == kNig) {
         const double xp = fmin(kTailExponent / (alpha - beta - Lp), kXCap);
@@ -261,6 +269,33 @@ hipError_t launch_first_order_tables(const lll_plan &p, hipStream_t st) {
     if (!p.d.k2) return hipErrorInvalidValue;
     return p.precision == LLL_FP64 ? launch_first_order_t<double>(p, st)
                                    : launch_first_order_t<float>(p, st);
+}
+
+namespace {
+
+// New initial forwards and a parallel shift of each rate's vol curve:
+// vol[k][r] = vol_base[k][r] + shift[r] for the live rates r >= k / s.
+__global__ void __launch_bounds__(256) set_inputs_kernel(const double *__restrict__ L0_in,
+                                                         const double *__restrict__ shift,
+                                                         const double *__restrict__ vol_base,
+                                                         double *__restrict__ L0,
+                                                         double *__restrict__ vol, int N, int s) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (L0_in && i < N) L0[i] = L0_in[i];
+    if (shift && i < N * s * N) {
+        const int k = i / N, r = i % N;
+        vol[i] = vol_base[i] + (r >= k / s ? shift[r] : 0.0);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_set_inputs(const lll_plan &p, const double *L0_dev, const double *shift_dev,
+                             hipStream_t st) {
+    const int n = shift_dev ? p.K * p.N : p.N;
+    hipLaunchKernelGGL(set_inputs_kernel, dim3((n + 255) / 256), dim3(256), 0, st, L0_dev,
+                       shift_dev, p.d.vol_base, p.d.L0, p.d.vol, p.N, p.s);
+    return hipGetLastError();
 }
 
 hipError_t launch_precompute(const lll_plan &p, hipStream_t st) {

@@ -116,7 +116,8 @@ def test_binding_constants_match_the_header():
     import paper_1006_3340_amd._lib as L
     text = open(os.path.join(ROOT, "include", "lll.h")).read()
     enum = dict((k, int(v)) for k, v in re.findall(r"\bLLL_([A-Z_0-9]+) = (\d+)", text))
-    for name in ("FULL", "PICARD", "FROZEN", "FIRST_ORDER", "SECOND_ORDER", "PICARD_MP", "EXACT"):
+    for name in ("FULL", "PICARD", "FROZEN", "FIRST_ORDER", "SECOND_ORDER", "PICARD_MP", "EXACT",
+                 "MLP_DRIFT"):
         assert getattr(L, name) == enum[name], name
         assert lll.SCHEMES[name.lower()] == enum[name], name
     defines = dict((k, int(v)) for k, v in re.findall(r"#define LLL_([A-Z_0-9]+) (\d+)", text))

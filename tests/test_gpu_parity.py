@@ -488,24 +488,27 @@ def test_greeks_full_size_structure_and_fourier(gpu_lib):
 
 @pytest.mark.parametrize("product", [0, 1])
 def test_autograd_function(gpu_lib, product):
+    """The device-resident autograd op: CUDA inputs, prices and gradients on the
+    device; the forward prices equal a host-created plan's, the backward is the
+    single-sweep vector-Jacobian product w^T J up to FP32 summation order."""
     import torch
-    from paper_1006_3340_amd.autograd import CapletPrice
+    from paper_1006_3340_amd.autograd import CapletPricer
     N = 8
     ts = _swaption_greeks_structure(N) if product else _greeks_structure(N)
     base = np.full(N, 0.12)
-    L0 = torch.tensor(ts.L0, dtype=torch.float64, requires_grad=True)
-    lv = torch.tensor(base, dtype=torch.float64, requires_grad=True)
-    w = torch.linspace(1.0, 2.0, N, dtype=torch.float64)
-    P = CapletPrice.apply(L0, lv, ts, 4096, 1, base)
-    (P * w).sum().backward()
-    with gpu_lib.Plan(ts, precision=0, max_paths=4096) as plan:
-        plan.greeks(4096, seed=1)
-        g = plan.greeks_results()
-    assert np.allclose(P.detach().numpy(), g["price"], rtol=1e-12, atol=0)
-    # the backward is the single-sweep vector-Jacobian product: w^T J up to
-    # FP32 summation order
-    for got, J in ((L0.grad.numpy(), g["dP_dL0"]), (lv.grad.numpy(), g["dP_dvol"])):
-        ref = w.numpy() @ J
+    L0 = torch.tensor(ts.L0, dtype=torch.float64, device="cuda", requires_grad=True)
+    lv = torch.tensor(base, dtype=torch.float64, device="cuda", requires_grad=True)
+    w = torch.linspace(1.0, 2.0, N, dtype=torch.float64, device="cuda")
+    with CapletPricer(ts, 4096, seed=1, base_levels=base) as price_fn:
+        P = price_fn(L0, lv)
+        assert P.is_cuda and P.shape == (N,)
+        (P * w).sum().backward()
+        with gpu_lib.Plan(ts, precision=0, max_paths=4096) as plan:
+            plan.greeks(4096, seed=1)
+            g = plan.greeks_results()
+    assert np.allclose(P.detach().cpu().numpy(), g["price"], rtol=1e-12, atol=0)
+    for got, J in ((L0.grad.cpu().numpy(), g["dP_dL0"]), (lv.grad.cpu().numpy(), g["dP_dvol"])):
+        ref = w.cpu().numpy() @ J
         assert np.allclose(got, ref, rtol=1e-5, atol=1e-6 * np.max(np.abs(ref))), (got, ref)
 
 
