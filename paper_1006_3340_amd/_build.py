@@ -14,7 +14,7 @@ LIB = os.path.join(HERE, "liblll.so")
 SOURCES = ["abi.hip", "precompute.hip", "paths.hip", "batched.hip", "adjoint.hip",
            "mlp_train.hip", "mlp_path.hip", "mlp_host.hip", "picard_mp.hip",
            "fma_probe.hip", "exact.hip", "noalloc.hip"] + sorted(
-    f for f in os.listdir(CSRC) if f.startswith(("bucket_", "adjoint_b")) and f.endswith(".hip"))
+    f for f in os.listdir(CSRC) if f.startswith(("bucket_", "adjoint_b", "batched_b")) and f.endswith(".hip"))
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -592,6 +592,11 @@ int lll_batch_destroy(lll_batch *batch) {
     if (batch->counter) (void)hipFree(batch->counter);
     for (int i = 0; i < 2; ++i)
         if (batch->ev[i]) (void)hipEventDestroy(batch->ev[i]);
+    for (int k = 0; k < lll::kBatchBuckets; ++k) {
+        if (batch->side[k]) (void)hipStreamDestroy(batch->side[k]);
+        if (batch->join[k]) (void)hipEventDestroy(batch->join[k]);
+    }
+    if (batch->fork) (void)hipEventDestroy(batch->fork);
     delete batch;
     return LLL_OK;
 }
@@ -624,7 +629,7 @@ int lll_batch_create(const lll_term_structure *ts, int n_ts, int64_t max_paths_e
     b->max_paths_each = max_paths_each;
     for (int i = 0; i < n_ts; ++i) {
         lll_plan *p = nullptr;
-        int rc = create_plan(&ts[i], LLL_FP32, max_paths_each, LLL_N_MAX, &p);
+        int rc = create_plan(&ts[i], LLL_FP32, max_paths_each, 0, &p);
         if (rc != LLL_OK) {
             lll_batch_destroy(b);
             return rc;
@@ -634,10 +639,20 @@ int lll_batch_create(const lll_term_structure *ts, int n_ts, int64_t max_paths_e
     b->max_items = static_cast<int>(items);
     hipError_t e = hipMalloc(&b->args, n_ts * lll::batch_args_bytes());
     if (e == hipSuccess) e = hipMalloc(&b->items, (size_t)b->max_items * lll::batch_item_bytes());
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&b->counter), 256);
+    if (e == hipSuccess)
+        e = hipMalloc(reinterpret_cast<void **>(&b->counter), 64 * sizeof(int) * lll::kBatchBuckets);
     if (e != hipSuccess) {
         lll_batch_destroy(b);
         return fail(LLL_ENOMEM, "device allocation: %s", hipGetErrorString(e));
+    }
+    e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+    for (int k = 0; k < lll::kBatchBuckets && e == hipSuccess; ++k) {
+        e = hipStreamCreateWithFlags(&b->side[k], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming);
+    }
+    if (e != hipSuccess) {
+        lll_batch_destroy(b);
+        return hip_fail(e, "creating the batch's streams");
     }
     *batch_out = b;
     return LLL_OK;

@@ -1,0 +1,10 @@
+// batched_b32.hip -- persistent batched kernels of the 32-slot register bucket.
+#define LLL_BUCKET_TU
+#define LLL_BATCH_BUCKET_TU
+#include "batched_kernel.hpp"
+
+namespace lll {
+namespace batch {
+LLL_BATCH_BUCKET_DECL(, 32)
+}  // namespace batch
+}  // namespace lll

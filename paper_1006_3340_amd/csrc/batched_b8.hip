@@ -1,0 +1,10 @@
+// batched_b8.hip -- persistent batched kernels of the 8-slot register bucket.
+#define LLL_BUCKET_TU
+#define LLL_BATCH_BUCKET_TU
+#include "batched_kernel.hpp"
+
+namespace lll {
+namespace batch {
+LLL_BATCH_BUCKET_DECL(, 8)
+}  // namespace batch
+}  // namespace lll

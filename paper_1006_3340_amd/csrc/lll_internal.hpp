@@ -96,13 +96,20 @@ struct lll_plan {
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 
+namespace lll {
+constexpr int kBatchBuckets = 5;  // register buckets of 40, 32, 24, 16 and 8 slots
+}
+
 struct lll_batch {
-    std::vector<lll_plan *> plans;   // one per structure, 40-slot bucket, FP32
+    std::vector<lll_plan *> plans;   // one per structure, its own register bucket, FP32
     int64_t max_paths_each = 0, n_paths_each = 0;
     void *args = nullptr;            // device PathArgs<float>[n]
-    void *items = nullptr;           // device work items
-    int *counter = nullptr;          // device work counter
+    void *items = nullptr;           // device work items, grouped by bucket
+    int *counter = nullptr;          // device work counters, one per bucket (64 ints apart)
     int n_items = 0, max_items = 0;
+    int bucket_begin[lll::kBatchBuckets] = {}, bucket_end[lll::kBatchBuckets] = {};
+    hipStream_t side[lll::kBatchBuckets] = {};  // the buckets' launch streams (default priority)
+    hipEvent_t fork = nullptr, join[lll::kBatchBuckets] = {};
     bool executed = false, timing = false, timed = false;
     hipEvent_t ev[2] = {nullptr, nullptr};
 };
