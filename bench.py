@@ -567,6 +567,7 @@ def main(argv=None) -> int:
         print(json.dumps({"error": "one-shot prices differ from the plan's"}))
         return 1
     fma_probe = lll.fp32_fma_peak()   # measured non-packed FP32 FMA ceiling, TFLOP/s
+    mix_probe = lll.fp32_mix_peak()   # the quadrature recursion's instruction mix, TFLOP/s
 
     path_steps = n * ts.n_steps * len(schemes) * args.steps
     value = path_steps / elapsed
@@ -605,13 +606,17 @@ def main(argv=None) -> int:
                      "achieved": fl_dom / (ms_dom / 1e3) / 1e12, "peak": PEAK_FP32 / 1e12,
                      "unit": "TFLOP/s", "frac": fl_dom / (ms_dom / 1e3) / PEAK_FP32,
                      "traffic": TRAFFIC_BYTES.get(kernel_hash(), {}).get(dom),
-                     # the quoted FP32 peak counts dual-issue packed FMAs, which
-                     # this build keeps out of its code: one FMA per lane and
-                     # cycle is the reachable ceiling (quoted / 2), also measured
-                     # on this GPU by the library's FMA probe
+                     # the quoted FP32 peak counts packed FMAs, which this build
+                     # keeps out of its code.  Measured on this GPU: FMAs with
+                     # scalar-register operands (the FMA probe) run near one per
+                     # lane and cycle (quoted / 2); the recursion's own mix (two
+                     # FMAs with a scalar table operand, one on vector registers,
+                     # per node and rate) is the attainable ceiling of the kernel
                      "single_issue_peak": PEAK_FP32 / 2 / 1e12,
                      "frac_of_single_issue": fl_dom / (ms_dom / 1e3) / (PEAK_FP32 / 2),
                      "fma_probe_tflops": fma_probe,
+                     "mix_ceiling_tflops": mix_probe,
+                     "frac_of_mix_ceiling": fl_dom / (ms_dom / 1e3) / 1e12 / mix_probe,
                      "kernel_hash": kernel_hash()},
         "schemes": per_scheme,
         "wall_s": wall,

@@ -490,6 +490,16 @@ int lll_price_caplets_batched(const lll_term_structure *ts, int n_ts, int64_t n_
  * buffer. */
 int lll_fp32_fma_peak(double *tflops_host, void *stream);
 
+/* The attainable ceiling of the quadrature recursion (the path kernels'
+ * coupling loop): throughput in TFLOP/s of its instruction mix -- per node and
+ * rate two FMAs whose second operand is a wave-uniform table entry held in a
+ * scalar register and one FMA on vector registers -- on every lane of a full
+ * grid, best of 3 timed runs.  On gfx950 a vector instruction with a
+ * scalar-register operand issues at about the single-issue rate while one on
+ * vector registers alone can issue faster, so this mix sits between the plain
+ * FMA probe and the quoted peak.  Synchronous; allocates a small buffer. */
+int lll_fp32_mix_peak(double *tflops_host, void *stream);
+
 /* Philox-4x32-10 words computed on the device for n counters ctr_host[n][4]
  * and keys key_host[n][2]; out_host[n][4]. */
 int lll_philox(const uint32_t *ctr_host, const uint32_t *key_host, int64_t n,

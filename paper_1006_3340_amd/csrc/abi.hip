@@ -491,6 +491,13 @@ int lll_fp32_fma_peak(double *tflops_host, void *stream) {
     return LLL_OK;
 }
 
+int lll_fp32_mix_peak(double *tflops_host, void *stream) {
+    if (!tflops_host) return fail(LLL_EINVAL, "tflops_host is NULL");
+    hipError_t e = lll::measure_mix_peak(as_stream(stream), tflops_host);
+    if (e != hipSuccess) return hip_fail(e, "instruction-mix probe");
+    return LLL_OK;
+}
+
 int lll_philox(const uint32_t *ctr_host, const uint32_t *key_host, int64_t n, uint32_t *out_host,
                void *stream) {
     if (!ctr_host || !key_host || !out_host) return fail(LLL_EINVAL, "NULL argument");

@@ -244,11 +244,18 @@ __device__ __forceinline__ void exact_step(const PathArgs<Real> &a, cptr<Real> k
     exact_rates<Real, NMAX, NMAX - 1, J0>(a, kstep, k, dH, r, om, Real(1), X, wbuf);
 }
 
+// The first live slot j0 = NMAX - N + m is at least NMAX - LLL_N_MAX_EXACT:
+// only those slots get code (J0 = kExactLow + Js).
+template <int NMAX>
+constexpr int kExactLow = NMAX > LLL_N_MAX_EXACT ? NMAX - LLL_N_MAX_EXACT : 0;
+
 template <typename Real, int NMAX, int... Js>
 __device__ __forceinline__ void dispatch_exact_step(std::integer_sequence<int, Js...>, int j0,
                                                     const PathArgs<Real> &a, cptr<Real> kstep,
                                                     int k, Real dH, Real (&X)[NMAX], Real *wbuf) {
-    (void)((j0 == Js ? (exact_step<Real, NMAX, Js>(a, kstep, k, dH, X, wbuf), 0) : 0) + ...);
+    constexpr int lo = kExactLow<NMAX>;
+    (void)((j0 == lo + Js ? (exact_step<Real, NMAX, lo + Js>(a, kstep, k, dH, X, wbuf), 0) : 0) +
+           ...);
 }
 
 template <typename Real, int NMAX, int PRODUCT>
@@ -275,8 +282,8 @@ __global__ void __launch_bounds__(kBlock) exact_kernel(PathArgs<Real> a, cptr<Re
             make_uint4(static_cast<uint32_t>(k), p_lo, p_hi, a.stream_word), a.key0, a.key1);
         const Real dH = static_cast<Real>(increment(w, cst, a.beta, brownian, nullptr));
         const int j0 = a.off + m;
-        dispatch_exact_step<Real, NMAX>(std::make_integer_sequence<int, NMAX>{}, j0, a,
-                                        kex + exact_step_base(a.N, a.s, k), k, dH, X, wbuf);
+        dispatch_exact_step<Real, NMAX>(std::make_integer_sequence<int, NMAX - kExactLow<NMAX>>{}, j0,
+                                        a, kex + exact_step_base(a.N, a.s, k), k, dH, X, wbuf);
         if (++js == a.s) {
             detail::dispatch_payoff<Real, NMAX, PRODUCT>(std::make_integer_sequence<int, NMAX>{}, j0,
                                                          a, m, gid, active, X);

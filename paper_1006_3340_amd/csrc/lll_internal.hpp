@@ -164,6 +164,9 @@ hipError_t launch_picard_mp(const lll_plan &p, int64_t n_paths, int64_t path_off
 
 // fma_probe.hip: throughput of plain FP32 FMAs (TFLOP/s, best of 3 timed runs)
 hipError_t measure_fma_peak(hipStream_t st, double *tflops);
+// the same for the quadrature recursion's instruction mix (two FMAs with a
+// scalar-register table operand, one on vector registers, per node and rate)
+hipError_t measure_mix_peak(hipStream_t st, double *tflops);
 
 // paths.hip
 // LLL_EXACT: entries of the cumulant table and the launch (table build, paths).

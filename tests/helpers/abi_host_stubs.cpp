@@ -28,6 +28,7 @@ hipError_t launch_reduce(const lll_plan &, int64_t, hipStream_t) { return hipErr
 hipError_t launch_batched(const lll_batch &, int, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_picard_mp(const lll_plan &, int64_t, int64_t, uint64_t, double *, hipStream_t) { return hipErrorNotSupported; }
 hipError_t measure_fma_peak(hipStream_t, double *) { return hipErrorNotSupported; }
+hipError_t measure_mix_peak(hipStream_t, double *) { return hipErrorNotSupported; }
 hipError_t launch_greeks_vjp(const lll_plan &, int64_t, uint64_t, const double *, const double *, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_increments(const lll_plan &, int, int64_t, int64_t, uint64_t, double *, double *, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_precompute(const lll_plan &, hipStream_t) { return hipErrorNotSupported; }
