@@ -1,6 +1,7 @@
 // abi.hip -- the extern "C" boundary: validation, plan lifetime, launches.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -148,7 +149,7 @@ hipError_t dalloc(T **p, size_t n) {
 
 void free_tables(lll::DeviceTables &d) {
     void *ptrs[] = {d.tenor, d.delta, d.L0, d.vol, d.strikes, d.x, d.w, d.kappa, d.E, d.b0,
-                    d.steps, d.lam_pm, d.vol_base, d.ew, d.lam, d.drift0, d.frozen, d.dt, d.cinv, d.k2, d.kex, d.L0s,
+                    d.steps, d.lam_pm, d.vol_base, d.ew, d.lam, d.drift0, d.frozen, d.dt, d.cinv, d.k2, d.kex, d.xex, d.L0s,
                     d.deltas, d.partials, d.chunks, d.sums, d.results};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -340,13 +341,19 @@ int lll_plan_execute(lll_plan *plan, int scheme, int64_t n_paths, int64_t path_o
     if (exact && plan->N > LLL_N_MAX_EXACT)
         return fail(LLL_EUNSUPPORTED, "LLL_EXACT sums 2^(N-1-i) terms per rate: N=%d > %d",
                     plan->N, LLL_N_MAX_EXACT);
-    if (exact && !plan->d.kex) {
+    if (exact && (!plan->d.kex || !plan->d.xex)) {
         const size_t esz = plan->precision == LLL_FP64 ? sizeof(double) : sizeof(float);
-        hipError_t ea =
-            hipMalloc(&plan->d.kex, (size_t)lll::exact_table_entries(plan->N, plan->s) * esz);
+        const int64_t nk = std::max<int64_t>(1, lll::exact_table_entries(plan->N, plan->s));
+        hipError_t ea = plan->d.kex ? hipSuccess : hipMalloc(&plan->d.kex, (size_t)nk * esz);
         if (ea != hipSuccess) {
             plan->d.kex = nullptr;
             return fail(LLL_ENOMEM, "exact-drift table: %s", hipGetErrorString(ea));
+        }
+        ea = hipMalloc(&plan->d.xex,
+                       (size_t)lll::exact_state_entries(plan->N, plan->max_paths) * esz);
+        if (ea != hipSuccess) {
+            plan->d.xex = nullptr;
+            return fail(LLL_ENOMEM, "exact-drift path states: %s", hipGetErrorString(ea));
         }
     }
     if (scheme == LLL_FIRST_ORDER && !plan->d.k2) {

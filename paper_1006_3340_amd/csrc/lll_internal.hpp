@@ -39,6 +39,7 @@ struct DeviceTables {
     void *cinv = nullptr;      // [nmax]  1 / (delta L0)
     void *k2 = nullptr;        // [K][nmax][nmax] first-order coefficients (allocated on first use)
     void *kex = nullptr;       // exact-drift cumulant table (allocated on first use)
+    void *xex = nullptr;       // [N][max_paths] exact-drift path states (allocated on first use)
     // maturity-parallel PICARD (FP32, allocated on first use)
     void *mp_ewq = nullptr;       // [K][N][Q] (E, W E dt)
     float *mp_ell = nullptr;      // [chunk/4][s N (N+1)/2][4] ell at the predictor, live rates
@@ -171,6 +172,7 @@ hipError_t measure_mix_peak(hipStream_t st, double *tflops);
 // paths.hip
 // LLL_EXACT: entries of the cumulant table and the launch (table build, paths).
 int64_t exact_table_entries(int N, int s);
+int64_t exact_state_entries(int N, int64_t max_paths);
 hipError_t launch_exact(const lll_plan &p, int64_t n_paths, int64_t path_offset, uint64_t seed,
                         double *path_fix, hipStream_t st);
 hipError_t launch_paths(const lll_plan &p, int scheme, int64_t n_paths, int64_t path_offset,
