@@ -500,6 +500,13 @@ int lll_fp32_fma_peak(double *tflops_host, void *stream);
  * FMA probe and the quoted peak.  Synchronous; allocates a small buffer. */
 int lll_fp32_mix_peak(double *tflops_host, void *stream);
 
+/* The attainable ceiling of the exact-drift kernel's products: throughput in
+ * TFLOP/s (multiply-add = 2) of a stream of independent FP32 matrix-core
+ * instructions (v_mfma_f32_16x16x4f32, operands in registers, no memory
+ * traffic) on 4 wavefronts per SIMD of every compute unit, best of 3 timed
+ * runs.  Synchronous; allocates a small buffer. */
+int lll_fp32_mfma_peak(double *tflops_host, void *stream);
+
 /* Philox-4x32-10 words computed on the device for n counters ctr_host[n][4]
  * and keys key_host[n][2]; out_host[n][4]. */
 int lll_philox(const uint32_t *ctr_host, const uint32_t *key_host, int64_t n,

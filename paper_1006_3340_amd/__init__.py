@@ -9,7 +9,7 @@ from ._lib import (EXACT, FIRST_ORDER, FP32, FP64, FROZEN, FULL, MLP_DRIFT, N_MA
                    N_MAX_EXACT, N_MAX_MP, PICARD, PICARD_MP, SECOND_ORDER,
                    Batch, LLLError, Mlp, Plan, caplet_greeks, load, philox, price_caplets,
                    price_caplets_batched, price_caplets_static, fp32_fma_peak, fp32_mix_peak,
-                   version)
+                   fp32_mfma_peak, version)
 
 SCHEMES = {"full": FULL, "picard": PICARD, "frozen": FROZEN, "first_order": FIRST_ORDER,
            "second_order": SECOND_ORDER, "picard_mp": PICARD_MP, "exact": EXACT,

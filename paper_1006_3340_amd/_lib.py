@@ -31,7 +31,7 @@ EXPORTS = ["lll_version", "lll_last_error", "lll_plan_create", "lll_plan_execute
            "lll_batch_execute", "lll_batch_results", "lll_batch_set_timing", "lll_batch_timing",
            "lll_batch_destroy", "lll_plan_greeks", "lll_plan_greeks_results", "lll_plan_greeks_vjp",
            "lll_plan_greeks_vjp_results", "lll_caplet_greeks", "lll_price_caplets_batched",
-           "lll_fp32_fma_peak", "lll_fp32_mix_peak", "lll_price_caplets_static",
+           "lll_fp32_fma_peak", "lll_fp32_mix_peak", "lll_fp32_mfma_peak", "lll_price_caplets_static",
            "lll_mlp_create", "lll_mlp_destroy", "lll_mlp_params", "lll_mlp_generate",
            "lll_mlp_info", "lll_mlp_set_box", "lll_mlp_pairs", "lll_mlp_train", "lll_mlp_eval",
            "lll_plan_execute_mlp", "lll_plan_mlp_stats", "lll_mlp_train_dev",
@@ -98,6 +98,7 @@ def load():
                                               dpp, dpp, vp]
     lib.lll_fp32_fma_peak.argtypes = [dp, vp]
     lib.lll_fp32_mix_peak.argtypes = [dp, vp]
+    lib.lll_fp32_mfma_peak.argtypes = [dp, vp]
     lib.lll_philox.argtypes = [u32p, u32p, i64, u32p, vp]
     lib.lll_plan_increments.argtypes = [vp, i32, i64, i64, u64, dp, dp, vp]
     lib.lll_plan_tables.argtypes = [vp, dp, dp, dp, dp, dp, vp]
@@ -468,6 +469,15 @@ def fp32_mix_peak(stream=None) -> float:
     lib = load()
     out = np.zeros(1)
     _check(lib.lll_fp32_mix_peak(_dp(out), stream_handle(stream)))
+    return float(out[0])
+
+
+def fp32_mfma_peak(stream=None) -> float:
+    """lll_fp32_mfma_peak: measured throughput of independent FP32 16x16x4
+    matrix-core instructions, TFLOP/s."""
+    lib = load()
+    out = np.zeros(1)
+    _check(lib.lll_fp32_mfma_peak(_dp(out), stream_handle(stream)))
     return float(out[0])
 
 

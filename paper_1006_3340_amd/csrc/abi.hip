@@ -343,7 +343,7 @@ int lll_plan_execute(lll_plan *plan, int scheme, int64_t n_paths, int64_t path_o
                     plan->N, LLL_N_MAX_EXACT);
     if (exact && (!plan->d.kex || !plan->d.xex)) {
         const size_t esz = plan->precision == LLL_FP64 ? sizeof(double) : sizeof(float);
-        const int64_t nk = std::max<int64_t>(1, lll::exact_table_entries(plan->N, plan->s));
+        const int64_t nk = lll::exact_table_entries(plan->N, plan->s);
         hipError_t ea = plan->d.kex ? hipSuccess : hipMalloc(&plan->d.kex, (size_t)nk * esz);
         if (ea != hipSuccess) {
             plan->d.kex = nullptr;
@@ -502,6 +502,13 @@ int lll_fp32_mix_peak(double *tflops_host, void *stream) {
     if (!tflops_host) return fail(LLL_EINVAL, "tflops_host is NULL");
     hipError_t e = lll::measure_mix_peak(as_stream(stream), tflops_host);
     if (e != hipSuccess) return hip_fail(e, "instruction-mix probe");
+    return LLL_OK;
+}
+
+int lll_fp32_mfma_peak(double *tflops_host, void *stream) {
+    if (!tflops_host) return fail(LLL_EINVAL, "tflops_host is NULL");
+    hipError_t e = lll::measure_mfma_peak(as_stream(stream), tflops_host);
+    if (e != hipSuccess) return hip_fail(e, "matrix-core probe");
     return LLL_OK;
 }
 

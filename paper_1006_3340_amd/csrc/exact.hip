@@ -65,6 +65,10 @@ using detail::PathArgs;
 constexpr int kNX = LLL_N_MAX_EXACT;  // slots
 constexpr int kG = 6;                 // low group: the last kG slots, the 64 rows
 constexpr int kRows = 1 << kG;
+// Table chunks (4 columns, 256 entries) loaded ahead of the products; the
+// table is padded by as many chunks so that these loads need no bound.
+constexpr int kAhead = 4;
+constexpr int64_t kTablePad = kAhead * 256;
 
 // High rates of slot J (slots J+1 .. NX-G-1).
 __host__ __device__ constexpr int high_rates(int J) {
@@ -114,20 +118,32 @@ struct Mfma<double> {
     }
 };
 
-// One thread per table entry of step k (blockIdx.y strides over the steps).
+// One thread per table entry.  A step's entries are a whole number of blocks
+// (64 rows times a multiple of 4 columns per slot), so every block lies in one
+// step: the block finds its period, step and offset (uniform work).
 template <typename Real>
 __global__ void __launch_bounds__(256) exact_table_kernel(const double *__restrict__ vol, int N,
-                                                          int s, int K, int driver, double alpha,
+                                                          int s, int driver, double alpha,
                                                           double beta, double delta_nig, double c,
                                                           Real *__restrict__ kex) {
     const bool nig = driver == LLL_DRIVER_NIG;
     const int offx = kNX - N;
-    for (int k = blockIdx.y; k < K; k += gridDim.y) {
-        const int m = k / s;
-        const int j0 = offx + m;
-        int64_t q = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-        if (q >= step_entries(N, m)) continue;
-        const int64_t flat = step_base(N, s, k) + q;
+    int64_t b = blockIdx.x, base = 0;  // base: entries of the periods before m
+    int m = 0;
+    int64_t bm = step_entries(N, 0) / 256;  // blocks per step of period m
+    while (m < N - 1 && b >= s * bm) {
+        b -= s * bm;
+        base += s * bm * 256;
+        ++m;
+        bm = step_entries(N, m) / 256;
+    }
+    if (bm == 0) return;
+    const int js = static_cast<int>(b / bm);
+    const int k = m * s + js;
+    int64_t q = (b % bm) * 256 + threadIdx.x;
+    const int64_t flat = base + js * bm * 256 + q;
+    const int j0 = offx + m;
+    {
         int J = j0;
         while (q >= static_cast<int64_t>(kRows) * slot_cols(J)) {
             q -= static_cast<int64_t>(kRows) * slot_cols(J);
@@ -179,7 +195,7 @@ __device__ __forceinline__ void slot_sum(const StepState<Real, T> &st, cptr<Real
     constexpr int lb = hk < 3 ? hk : 3;    // low bits of kc: the unrolled inner loop
     constexpr int hb = hk - lb;            // high bits of kc: the outer loop
     constexpr int ni = 1 << lb, no = 1 << hb, nkc = ni * no;
-    constexpr int D = ni < 4 ? ni : 4;  // chunks of the table in flight
+    constexpr int D = ni < kAhead ? ni : kAhead;  // chunks of the table in flight
     const int g = lane / 16;
     // P(u) of column u = 4 kc + g = bin[kc % ni] stk[0]: the two low bits of u
     // from g (slots J+1, J+2) and the low bits of kc (slots J+3 ..) in bin, the
@@ -227,16 +243,20 @@ __device__ __forceinline__ void slot_sum(const StepState<Real, T> &st, cptr<Real
             for (int i = 0; i < ni; ++i) B[c][i] = bin[c][i] * stk[c][0];
 #pragma unroll
         for (int i = 0; i < ni; ++i) {
+            // keep each chunk's products and its ring load together: left to
+            // itself the scheduler hoists the loads to the iteration's top and
+            // drains them at its end, which breaks the ring at the back edge
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int c = 0; c < T; ++c)
 #pragma unroll
                 for (int rt = 0; rt < 4; ++rt)
                     acc[rt][c] = Mfma<Real>::run(A[i % D][rt], B[c][i], acc[rt][c]);
-            const int kn = ko * ni + i + D;  // the chunk this ring slot takes next
-            if (kn < nkc) {
+            // the chunk this ring slot takes next: past the slot's end it reads
+            // the next slot's entries or the table's padding, never used
+            const int kn = ko * ni + i + D;
 #pragma unroll
-                for (int rt = 0; rt < 4; ++rt) A[i % D][rt] = kp[(kn * 4 + rt) * kWave];
-            }
+            for (int rt = 0; rt < 4; ++rt) A[i % D][rt] = kp[(kn * 4 + rt) * kWave];
         }
         if constexpr (hb > 0) {
             // ko -> ko + 1: bit cb is set and the bits below it cleared
@@ -340,24 +360,40 @@ __global__ void __launch_bounds__(kBlock) exact_period_kernel(PathArgs<Real> a, 
     constexpr int se = Mfma<Real>::kElemLow ? kNX - 6 : kNX - 4;
     constexpr int sg = Mfma<Real>::kElemLow ? kNX - 4 : kNX - 6;
     const int64_t cum0 = slot_cum(j0);
+    // Driver increments: the four lane groups hold T tiles x SB steps, so each
+    // lane draws one increment per SB steps (lane group g: tile g % T, step
+    // g / T of the batch) and the steps read them with lane shuffles.
+    constexpr int SB = 4 / T;
+    Real inc = Real(0);
 #pragma unroll 1
     for (int js = 0; js < a.s; ++js) {
         const int k = m * a.s + js;
+        if (js % SB == 0) {
+            const int jd = js + g / T;
+            if (jd < a.s) {
+                const int64_t p = a.path_offset + p0 + 16 * (g % T) + n;
+                const uint4 w = philox4x32_10(
+                    make_uint4(static_cast<uint32_t>(m * a.s + jd), static_cast<uint32_t>(p),
+                               static_cast<uint32_t>(static_cast<uint64_t>(p) >> 32),
+                               a.stream_word),
+                    a.key0, a.key1);
+                inc = static_cast<Real>(increment(w, cst, a.beta, a.brownian != 0, nullptr));
+            }
+        }
         Real dH[T];
         StepState<Real, T> st;
 #pragma unroll
         for (int c = 0; c < T; ++c) {
-            const int64_t p = a.path_offset + pidx[c];
-            const uint4 w = philox4x32_10(
-                make_uint4(static_cast<uint32_t>(k), static_cast<uint32_t>(p),
-                           static_cast<uint32_t>(static_cast<uint64_t>(p) >> 32), a.stream_word),
-                a.key0, a.key1);
-            dH[c] = static_cast<Real>(increment(w, cst, a.beta, a.brownian != 0, nullptr));
+            dH[c] = __shfl(inc, 16 * ((js % SB) * T + c) + n, kWave);
             st.q[c] = Real(1);
 #pragma unroll
             for (int J = 0; J < kNX; ++J) {  // delta L of the live slots, 0 for the others
-                const Real rr = Real(1) / (a.cinv[J - offx + a.off] * exp(-xw[J][16 * c + n]));
-                st.r[c][J] = J >= j0 ? rr : Real(0);
+                Real rr = Real(0);
+                if (J >= j0) {
+                    const int sl = J - offx + a.off;
+                    rr = static_cast<Real>(a.deltas[sl] * a.L0s[sl]) * exp(xw[J][16 * c + n]);
+                }
+                st.r[c][J] = rr;
             }
             const Real *r = st.r[c];
 #pragma unroll
@@ -438,12 +474,11 @@ hipError_t launch_exact_t(const lll_plan &p, int64_t n_paths, int64_t path_offse
     Real *kex = static_cast<Real *>(p.d.kex);
     Real *xs = static_cast<Real *>(p.d.xex);
     hipError_t e = hipSuccess;
-    const int64_t max_step = step_entries(p.N, 0);
-    if (max_step > 0) {
-        const dim3 tgrid(static_cast<unsigned>((max_step + 255) / 256),
-                         static_cast<unsigned>(std::min(p.K, 65535)));
-        hipLaunchKernelGGL(exact_table_kernel<Real>, tgrid, dim3(256), 0, st, p.d.vol, p.N, p.s,
-                           p.K, p.driver, p.alpha, p.beta, p.delta_nig, p.c, kex);
+    const int64_t blocks = step_base(p.N, p.s, p.K) / 256;
+    if (blocks > 0) {
+        hipLaunchKernelGGL(exact_table_kernel<Real>, dim3(static_cast<unsigned>(blocks)), dim3(256),
+                           0, st, p.d.vol, p.N, p.s, p.driver, p.alpha, p.beta, p.delta_nig, p.c,
+                           kex);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -474,7 +509,7 @@ hipError_t launch_exact_t(const lll_plan &p, int64_t n_paths, int64_t path_offse
 
 }  // namespace
 
-int64_t exact_table_entries(int N, int s) { return step_base(N, s, N * s); }
+int64_t exact_table_entries(int N, int s) { return step_base(N, s, N * s) + kTablePad; }
 
 int64_t exact_state_entries(int N, int64_t max_paths) {
     return static_cast<int64_t>(N) * max_paths;

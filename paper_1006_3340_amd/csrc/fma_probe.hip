@@ -65,7 +65,61 @@ __global__ void __launch_bounds__(256) mix_probe_kernel(
     out[t] = s;
 }
 
+// The matrix-core ceiling of the exact-drift kernel's products: a stream of
+// independent v_mfma_f32_16x16x4f32 (8 accumulators per wavefront, operands
+// in registers, no memory traffic) on 4 wavefronts per SIMD.
+__global__ void __launch_bounds__(256) mfma_probe_kernel(float *__restrict__ out, float a0, float b0,
+                                                         int iters) {
+    typedef float vec4 __attribute__((ext_vector_type(4)));
+    vec4 acc[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[j] = vec4{0.0f, 0.0f, 0.0f, 0.0f};
+    const float a = a0 + threadIdx.x * 1e-7f, b = b0;
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[j], 0, 0, 0);
+    }
+    float s = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s += (acc[j][0] + acc[j][1]) + (acc[j][2] + acc[j][3]);
+    out[blockIdx.x * blockDim.x + threadIdx.x] = s;  // keeps the products live
+}
+
 }  // namespace
+
+hipError_t measure_mfma_peak(hipStream_t st, double *tflops) {
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    const int blocks = cus * 4, threads = 256, iters = 2048;
+    float *out = nullptr;
+    e = hipMalloc(&out, (size_t)blocks * threads * sizeof(float));
+    if (e != hipSuccess) return e;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    double best = 0.0;
+    for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {
+        e = hipEventRecord(e0, st);
+        if (e != hipSuccess) break;
+        hipLaunchKernelGGL(mfma_probe_kernel, dim3(blocks), dim3(threads), 0, st, out, 1e-3f, 0.5f,
+                           iters);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        // 16 x 16 x 4 multiply-adds per instruction and wavefront
+        const double fl = (double)blocks * (threads / kWaveSize) * iters * 8 * (16.0 * 16 * 4 * 2);
+        if (e == hipSuccess && rep > 0 && ms > 0.0f) best = fmax(best, fl / (ms * 1e-3) / 1e12);
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(out);
+    *tflops = best;
+    return e;
+}
 
 hipError_t measure_mix_peak(hipStream_t st, double *tflops) {
     int dev = 0, cus = 0;

@@ -168,6 +168,7 @@ hipError_t measure_fma_peak(hipStream_t st, double *tflops);
 // the same for the quadrature recursion's instruction mix (two FMAs with a
 // scalar-register table operand, one on vector registers, per node and rate)
 hipError_t measure_mix_peak(hipStream_t st, double *tflops);
+hipError_t measure_mfma_peak(hipStream_t st, double *tflops);
 
 // paths.hip
 // LLL_EXACT: entries of the cumulant table and the launch (table build, paths).

@@ -18,6 +18,7 @@ hipError_t picard_mp_alloc(lll_plan &) { return hipErrorNotSupported; }
 size_t batch_args_bytes() { return 256; }
 size_t batch_item_bytes() { return 16; }
 int64_t exact_table_entries(int, int) { return 0; }
+int64_t exact_state_entries(int, int64_t) { return 0; }
 hipError_t launch_drift(const lll_plan &, int, const double *, int64_t, double *, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_exact(const lll_plan &, int64_t, int64_t, uint64_t, double *, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_paths(const lll_plan &, int, int64_t, int64_t, uint64_t, double *, hipStream_t) { return hipErrorNotSupported; }
@@ -29,6 +30,7 @@ hipError_t launch_batched(const lll_batch &, int, hipStream_t) { return hipError
 hipError_t launch_picard_mp(const lll_plan &, int64_t, int64_t, uint64_t, double *, hipStream_t) { return hipErrorNotSupported; }
 hipError_t measure_fma_peak(hipStream_t, double *) { return hipErrorNotSupported; }
 hipError_t measure_mix_peak(hipStream_t, double *) { return hipErrorNotSupported; }
+hipError_t measure_mfma_peak(hipStream_t, double *) { return hipErrorNotSupported; }
 hipError_t launch_greeks_vjp(const lll_plan &, int64_t, uint64_t, const double *, const double *, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_increments(const lll_plan &, int, int64_t, int64_t, uint64_t, double *, double *, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_precompute(const lll_plan &, hipStream_t) { return hipErrorNotSupported; }
