@@ -356,6 +356,13 @@ def exact_flops_per_path(ts) -> int:
     return sum(s * (2 * ((1 << (N - m)) - 1) + 8 * (N - m) + 40) for m in range(N))
 
 
+def exact_subset_flops_per_path(ts) -> int:
+    """The subset-sum part of exact_flops_per_path, the work the matrix cores
+    do: one multiply-add per subset term of every live rate and step."""
+    N, s = ts.n_rates, ts.steps_per_period
+    return sum(s * 2 * ((1 << (N - m)) - 1) for m in range(N))
+
+
 # The paper's own timing of its full solution (exact drift) on the example of
 # its Section 4: N = 9, 10^4 paths, 5 steps per period, Matlab on an 8-process
 # Intel i7 (another machine: context, not a target).
@@ -388,15 +395,26 @@ def bench_exact(lll, stream) -> dict:
     with lll.Plan(ts, precision=lll.FP32, max_paths=n) as plan:
         plan.set_timing(True)
         plan.execute(lll.EXACT, n, seed=1, stream=stream)   # warmup
-        plan.execute(lll.EXACT, n, seed=1, stream=stream)
-        ms = plan.timing()["paths"]
+        ms = []
+        for _ in range(3):
+            plan.execute(lll.EXACT, n, seed=1, stream=stream)
+            ms.append(plan.timing()["paths"])
+        ms = float(np.median(ms))
         pe = plan.results(stream)["price"]
         plan.execute(lll.FULL, n, seed=1, stream=stream)
         pf = plan.results(stream)["price"]
     fl = exact_flops_per_path(ts) * n
+    mfma_probe = lll.fp32_mfma_peak()   # measured FP32 16x16x4 matrix-core rate, TFLOP/s
+    achieved = exact_subset_flops_per_path(ts) * n / (ms / 1e3) / 1e12
     out["gpu_n20_fp32_65536"] = {
         "path_kernel_ms": ms, "path_steps_per_s": n * ts.n_steps / (ms / 1e3),
         "fp32_tflops": fl / (ms / 1e3) / 1e12, "frac_fp32_peak": fl / (ms / 1e3) / PEAK_FP32,
+        # the subset sums run on v_mfma_f32_16x16x4f32: their rate against the
+        # quoted dense FP32 matrix peak and the measured matrix-core ceiling
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32 / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved * 1e12 / PEAK_FP32,
+                     "mfma_ceiling_tflops": mfma_probe,
+                     "frac_of_mfma_ceiling": achieved / mfma_probe},
         "max_rel_diff_vs_full": float(np.max(np.abs(pe[pf > 0] / pf[pf > 0] - 1)))}
     return out
 
