@@ -34,17 +34,35 @@ PEAK_FP32 = 157.3e12   # MI355X vector FP32, FLOP/s
 # hash of the kernel sources they were taken on; any other hash reports null.
 TRAFFIC_BYTES = {"5c30cdeaefec0b71": {"full": 237235924, "picard": 232727024}}
 KERNEL_SOURCES = ["paper_1006_3340_amd/csrc/path_kernel.hpp",
-                  "paper_1006_3340_amd/csrc/lll_device.hpp",
-                  "paper_1006_3340_amd/_build.py"]
+                  "paper_1006_3340_amd/csrc/lll_device.hpp"]
+MLP_SOURCES = ["paper_1006_3340_amd/csrc/mlp_path.hip", "paper_1006_3340_amd/csrc/mlp.hpp",
+               "paper_1006_3340_amd/csrc/mlp_train.hip",
+               "paper_1006_3340_amd/csrc/path_kernel.hpp",
+               "paper_1006_3340_amd/csrc/lll_device.hpp"]
+# rocprofv3 --pmc figures of the surrogate pricing kernel at 2^20 paths
+# (profiles/mlp_kernels_mlp_n40_mfma_counters.md), by source hash: a changed
+# kernel reports none
+MLP_COUNTERS = {"dfa1400f18a0b1da": {
+    "source": "profiles/mlp_kernels_mlp_n40_mfma_counters.md",
+    "mlp_path_kernel_ms": 580.32, "clock_ghz": 2.38,
+    "counted_mfma_flop": 2.010e14, "counted_mfma_tflops": 346.4,
+    "mfma_busy": 0.139, "valu_busy": 0.863, "trans_share_of_valu": 0.193}}
+
+
+def source_hash(sources) -> str:
+    """Hash of kernel sources and the compile flags they are built with."""
+    import hashlib
+    from paper_1006_3340_amd import _build
+    h = hashlib.sha256()
+    for rel in sources:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    h.update(repr((_build.FLAGS, _build.PATH_FLAGS)).encode())
+    return h.hexdigest()[:16]
 
 
 def kernel_hash() -> str:
-    import hashlib
-    h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()[:16]
+    return source_hash(KERNEL_SOURCES)
 Q = 64
 METRIC = "path-steps/s: full Euler vs Picard vs MLP drift, at <=1e-4 rel caplet error"
 
@@ -272,7 +290,8 @@ def bench_mlp(lll, stream, n: int = 1 << 20, train_steps: int = 3000) -> dict:
             va += s * f["valu"]
     t = out["mlp"]["kernel_ms"] / 1e3
     out["mlp"].update({"mfma_tflops": mf * n / t / 1e12, "frac_bf16_peak": mf * n / t / PEAK_BF16,
-                       "valu_tflops": va * n / t / 1e12, "frac_fp32_peak": va * n / t / PEAK_FP32})
+                       "valu_tflops": va * n / t / 1e12, "frac_fp32_peak": va * n / t / PEAK_FP32,
+                       "counters": MLP_COUNTERS.get(source_hash(MLP_SOURCES))})
     for name in ("full", "picard", "first_order", "second_order"):
         fl = flops_per_path(ts, name) * n
         out[name]["frac_fp32_peak"] = fl / (out[name]["kernel_ms"] / 1e3) / PEAK_FP32
