@@ -32,7 +32,9 @@ PEAK_FP32 = 157.3e12   # MI355X vector FP32, FLOP/s
 # WRITE_SIZE runs of this benchmark, each scaled by the same counter's reading
 # for a 1 GiB device copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0), keyed by the
 # hash of the kernel sources they were taken on; any other hash reports null.
-TRAFFIC_BYTES = {"5c30cdeaefec0b71": {"full": 237235924, "picard": 232727024}}
+# calibrated HBM bytes per launch (profiles/path_kernel_gpu_n20_counters.md), by
+# source hash of the path kernels: a changed kernel reports none
+TRAFFIC_BYTES = {"43fbf0d6f153cb58": {"full": 237235924, "picard": 232727024}}
 KERNEL_SOURCES = ["paper_1006_3340_amd/csrc/path_kernel.hpp",
                   "paper_1006_3340_amd/csrc/lll_device.hpp"]
 MLP_SOURCES = ["paper_1006_3340_amd/csrc/mlp_path.hip", "paper_1006_3340_amd/csrc/mlp.hpp",
