@@ -59,18 +59,27 @@ def test_exact_paths_equal_full_paths_fp64(gpu_lib):
     assert np.all(np.abs(fb / fa - 1.0) < 1e-10)
 
 
-# N = 1 (no coupling), M <= 4 later rates only (N <= 5), the first register
-# block plus one or more enumerated bits (N = 6, 9, 17), and N = 20 itself
-@pytest.mark.parametrize("N,s", [(1, 3), (2, 2), (5, 2), (6, 2), (9, 1), (17, 1), (20, 1)])
-def test_exact_shapes(gpu_lib, oracle_mod, N, s):
+# The first rate's later rates as the kernel splits them: N = 1 (no coupling);
+# low group only (N <= 6: 2, 5, 6); one padded column chunk (N = 9); 2, 4 and
+# 8 chunks unrolled (N = 10, 11, 12: the table ring shorter than, equal to and
+# inside one unrolled group); the prefix-product stack over 1 and 5 chunk bits
+# (N = 13, 17); N = 20 itself.  FP64 plans (one 16-path tile per wavefront)
+# and FP32 plans (two tiles), 517 paths (a ragged last wavefront).
+@pytest.mark.parametrize("N,s", [(1, 3), (2, 2), (5, 2), (6, 2), (9, 1), (10, 1), (11, 1),
+                                 (12, 1), (13, 1), (17, 1), (20, 1)])
+@pytest.mark.parametrize("prec", [1, 0])
+def test_exact_shapes(gpu_lib, oracle_mod, N, s, prec):
     ts = workloads.make_structure(N, 0.5, 0.02 + 0.002 * np.arange(N), s,
                                   workloads.exp_decay_vol(), [0.9, 1.0, 1.1])
     n = 517
     ref = oracle_mod.Oracle(ts, seed=2).price(FULL, n)
-    with gpu_lib.Plan(ts, precision=1, max_paths=n) as plan:
+    with gpu_lib.Plan(ts, precision=prec, max_paths=n) as plan:
         plan.execute(EXACT, n, seed=2)
         got = plan.results()
-    assert np.allclose(got["price"], ref["price"], rtol=1e-9, atol=1e-300)
+    if prec == 1:
+        assert np.allclose(got["price"], ref["price"], rtol=1e-9, atol=1e-300)
+    else:
+        _check_prices(got, ref, ts, 1e-4)
 
 
 def test_exact_brownian_and_zero_vol(gpu_lib, oracle_mod):
@@ -110,3 +119,32 @@ def test_exact_errors(gpu_lib):
         with pytest.raises(gpu_lib.LLLError) as ei:
             bt.execute(EXACT, 64)
         assert ei.value.code == EINVAL
+
+
+def test_exact_bench_size_sampled_paths_and_reduction(gpu_lib, oracle_mod):
+    """The launch the bench times (N = 20, 2^16 paths, FP32, one period launch
+    per fixing on the matrix cores): sampled per-path fixings against the
+    oracle's FULL paths (whose drift equals the subset expansion to 1e-11) at
+    the FP32 path tolerance, the first and last path included, and the
+    reduction against the mean of the per-path payoffs recomputed on the host."""
+    import torch
+    ts = workloads.gpu_scale()
+    n = 1 << 16
+    o = oracle_mod.Oracle(ts, seed=1)
+    rng = np.random.default_rng(5)
+    sample = np.sort(rng.choice(n, size=12, replace=False))
+    sample[0], sample[-1] = 0, n - 1
+    fix = torch.empty((n, 2 * ts.n_rates), dtype=torch.float64, device="cuda")
+    with gpu_lib.Plan(ts, precision=0, max_paths=n) as plan:
+        plan.execute(EXACT, n, seed=1, path_fix=fix)
+        got = plan.results()
+    torch.cuda.synchronize()
+    f = fix.cpu().numpy()
+    Lg, Dg = f[:, 0::2], f[:, 1::2]
+    Lo, Do = o.paths(FULL, sample)
+    assert np.all(np.abs(Lg[sample] / Lo - 1.0) < 2e-5)
+    assert np.all(np.abs(Dg[sample] / Do - 1.0) < 2e-5)
+    pay = Dg[:, :, None] * np.maximum(Lg[:, :, None] - ts.strikes[None], 0.0)
+    B0T = ts.B0_T1 / np.prod(1.0 + ts.delta * ts.L0)
+    host_price = ts.delta[:, None] * B0T * pay.mean(axis=0)
+    assert np.allclose(got["price"], host_price, rtol=1e-12, atol=0)
