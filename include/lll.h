@@ -503,8 +503,9 @@ int lll_fp32_mix_peak(double *tflops_host, void *stream);
 /* The attainable ceiling of the exact-drift kernel's products: throughput in
  * TFLOP/s (multiply-add = 2) of a stream of independent FP32 matrix-core
  * instructions (v_mfma_f32_16x16x4f32, operands in registers, no memory
- * traffic) on 4 wavefronts per SIMD of every compute unit, best of 3 timed
- * runs.  Synchronous; allocates a small buffer. */
+ * traffic, 16 accumulators per wavefront) on 3 wavefronts per SIMD of every
+ * compute unit, best of 3 timed runs.  Synchronous; allocates a small
+ * buffer. */
 int lll_fp32_mfma_peak(double *tflops_host, void *stream);
 
 /* Philox-4x32-10 words computed on the device for n counters ctr_host[n][4]

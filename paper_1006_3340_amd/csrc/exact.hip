@@ -78,12 +78,23 @@ __host__ __device__ constexpr int high_rates(int J) {
 __host__ __device__ constexpr int slot_cols(int J) {
     return high_rates(J) <= 2 ? 4 : (1 << high_rates(J));
 }
-// Entries of slots 0 .. J-1.
+// Entries of slots 0 .. J-1: the slots with 2^h columns (h >= 3) sum to a
+// geometric series, the others have 4 columns each.
 __host__ __device__ constexpr int64_t slot_cum(int J) {
-    int64_t c = 0;
-    for (int j = 0; j < J; ++j) c += static_cast<int64_t>(kRows) * slot_cols(j);
-    return c;
+    constexpr int H0 = kNX - kG - 1;                 // high rates of slot 0
+    const int a = J < H0 - 2 ? J : H0 - 2;           // slots with 2^h columns
+    const int64_t geo = (int64_t(1) << (H0 + 1)) - (int64_t(1) << (H0 + 1 - a));
+    return kRows * geo + int64_t(kRows) * 4 * (J > H0 - 2 ? J - (H0 - 2) : 0);
 }
+constexpr bool slot_cum_checks() {
+    int64_t c = 0;
+    for (int J = 0; J <= kNX; ++J) {
+        if (slot_cum(J) != c) return false;
+        c += static_cast<int64_t>(kRows) * slot_cols(J);
+    }
+    return true;
+}
+static_assert(slot_cum_checks(), "slot offsets");
 // Entries of one step of period m (coupled live slots j0 .. NX-2, j0 = NX - N + m).
 __host__ __device__ inline int64_t step_entries(int N, int m) {
     return slot_cum(kNX - 1) - slot_cum(kNX - N + m);
@@ -177,6 +188,12 @@ __global__ void __launch_bounds__(256) exact_table_kernel(const double *__restri
     }
 }
 
+// Where period m's steps sit in the table (entries): the first step, the
+// step size and the offset of the first live slot within a step's layout.
+struct PeriodTable {
+    int64_t base, step, cum0;
+};
+
 template <typename Real, int T>
 struct StepState {
     Real r[T][kNX];                  // delta L of every slot (0 if fixed or absent)
@@ -186,8 +203,11 @@ struct StepState {
 
 // sum_t R(t) sum_u K_J[t][u] P(u) of each tile's path (the same value in the
 // four lanes of a path).
+// pre: this slot's first table chunk, loaded before the call; on return it
+// holds the next slot's (knext, when has_next), loaded while this slot runs.
 template <typename Real, int T, int J>
 __device__ __forceinline__ void slot_sum(const StepState<Real, T> &st, cptr<Real> kslot, int lane,
+                                         Real (&pre)[4], cptr<Real> knext, bool has_next,
                                          Real (&out)[T]) {
     typedef typename Mfma<Real>::vec4 vec4;
     constexpr int h = high_rates(J);
@@ -223,24 +243,33 @@ __device__ __forceinline__ void slot_sum(const StepState<Real, T> &st, cptr<Real
 #pragma unroll
         for (int b = 0; b <= hb; ++b) stk[c][b] = Real(1);
     }
-    vec4 acc[4][T];
+    // FP32: two accumulator sets, even and odd chunks, so that a product's
+    // accumulator is reused 16 products later instead of 8 (8 accumulators
+    // per wavefront reach 128 TFLOP/s of 16x16x4 FP32 products at two
+    // wavefronts per SIMD, 16 reach 150).  FP64 keeps one set: its registers
+    // hold one wavefront per SIMD either way.
+    constexpr int NS = (ni > 1 && sizeof(Real) == 4) ? 2 : 1;
+    vec4 acc[NS][4][T];
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt)
+    for (int h2 = 0; h2 < NS; ++h2)
 #pragma unroll
-        for (int c = 0; c < T; ++c) acc[rt][c] = vec4{0, 0, 0, 0};
+        for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+            for (int c = 0; c < T; ++c) acc[h2][rt][c] = vec4{0, 0, 0, 0};
     const cptr<Real> kp = kslot + lane;
     Real A[D][4];  // ring of table fragments, D chunks ahead of the products
 #pragma unroll
-    for (int d = 0; d < D; ++d)
+    for (int rt = 0; rt < 4; ++rt) A[0][rt] = pre[rt];
+#pragma unroll
+    for (int d = 1; d < D; ++d)
 #pragma unroll
         for (int rt = 0; rt < 4; ++rt) A[d][rt] = kp[(d * 4 + rt) * kWave];
+    if (has_next) {
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) pre[rt] = knext[lane + rt * kWave];
+    }
 #pragma unroll 1
     for (int ko = 0; ko < no; ++ko) {
-        Real B[T][ni];
-#pragma unroll
-        for (int c = 0; c < T; ++c)
-#pragma unroll
-            for (int i = 0; i < ni; ++i) B[c][i] = bin[c][i] * stk[c][0];
 #pragma unroll
         for (int i = 0; i < ni; ++i) {
             // keep each chunk's products and its ring load together: left to
@@ -248,10 +277,12 @@ __device__ __forceinline__ void slot_sum(const StepState<Real, T> &st, cptr<Real
             // drains them at its end, which breaks the ring at the back edge
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int c = 0; c < T; ++c)
+            for (int c = 0; c < T; ++c) {
+                const Real B = bin[c][i] * stk[c][0];
 #pragma unroll
                 for (int rt = 0; rt < 4; ++rt)
-                    acc[rt][c] = Mfma<Real>::run(A[i % D][rt], B[c][i], acc[rt][c]);
+                    acc[i % NS][rt][c] = Mfma<Real>::run(A[i % D][rt], B, acc[i % NS][rt][c]);
+            }
             // the chunk this ring slot takes next: past the slot's end it reads
             // the next slot's entries or the table's padding, never used
             const int kn = ko * ni + i + D;
@@ -280,7 +311,11 @@ __device__ __forceinline__ void slot_sum(const StepState<Real, T> &st, cptr<Real
         for (int rt = 0; rt < 4; ++rt) {
             Real row = Real(0);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) row = fma(st.pe[c][e], acc[rt][c][e], row);
+            for (int e = 0; e < 4; ++e) {
+                Real y = acc[0][rt][c][e];
+                if constexpr (NS > 1) y += acc[1][rt][c][e];
+                row = fma(st.pe[c][e], y, row);
+            }
             sum = fma(st.pt[c][rt], row, sum);
         }
         sum *= st.pg[c];
@@ -298,7 +333,8 @@ __device__ __forceinline__ void slot_sum(const StepState<Real, T> &st, cptr<Real
 template <typename Real, int T, int J>
 __device__ __forceinline__ void exact_slots(const PathArgs<Real> &a, StepState<Real, T> &st,
                                             cptr<Real> kstep, int64_t cum0, int k, int j0, int offx,
-                                            int lane, const Real (&dH)[T], Real (*xw)[16 * T]) {
+                                            int lane, const Real (&dH)[T], Real (*xw)[16 * T],
+                                            Real (&pre)[4]) {
     if constexpr (J >= 0) {
         if (J < j0) return;
         Real C[T];
@@ -306,7 +342,10 @@ __device__ __forceinline__ void exact_slots(const PathArgs<Real> &a, StepState<R
 #pragma unroll
             for (int c = 0; c < T; ++c) C[c] = Real(0);  // the last rate has no coupling
         } else {
-            slot_sum<Real, T, J>(st, kstep + (slot_cum(J) - cum0), lane, C);
+            // the next slot (J - 1) is coupled when it is live
+            constexpr int Jn = J > 0 ? J - 1 : 0;
+            slot_sum<Real, T, J>(st, kstep + (slot_cum(J) - cum0), lane, pre,
+                                 kstep + (slot_cum(Jn) - cum0), J > 0 && J - 1 >= j0, C);
 #pragma unroll
             for (int c = 0; c < T; ++c) {
                 st.q[c] *= Real(1) / (Real(1) + st.r[c][J + 1]);  // 1 - ell of slot J+1
@@ -318,15 +357,22 @@ __device__ __forceinline__ void exact_slots(const PathArgs<Real> &a, StepState<R
         const int n = lane % 16;
 #pragma unroll
         for (int c = 0; c < T; ++c) xw[J][16 * c + n] += fma(lam, dH[c], fma(-C[c], dt, d0));
-        exact_slots<Real, T, J - 1>(a, st, kstep, cum0, k, j0, offx, lane, dH, xw);
+        exact_slots<Real, T, J - 1>(a, st, kstep, cum0, k, j0, offx, lane, dH, xw, pre);
     }
 }
 
 // The s Euler steps of period m for 16 T paths per wavefront, the states in
 // the wavefront's LDS for the period (slot-major, compile-time offsets).
+// Two wavefronts per SIMD for FP32 plans (256 registers each; left to itself
+// the compiler takes ~300 and one), one for FP64.
+template <typename Real>
+constexpr int kWavesPerSimd = sizeof(Real) == 4 ? 2 : 1;
+
 template <typename Real, int T>
-__global__ void __launch_bounds__(kBlock) exact_period_kernel(PathArgs<Real> a, cptr<Real> kex,
-                                                              Real *__restrict__ xs, int m) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWavesPerSimd<Real>)))
+exact_period_kernel(PathArgs<Real> a, cptr<Real> kex,
+                                                              Real *__restrict__ xs, int m,
+                                                              PeriodTable pt) {
     __shared__ Real xl[kBlock / kWave][kNX][16 * T];
     const int lane = threadIdx.x % kWave;
     const int64_t wave = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) / kWave;
@@ -359,7 +405,7 @@ __global__ void __launch_bounds__(kBlock) exact_period_kernel(PathArgs<Real> a, 
     // the lane group g the other), bits 4-5 (row tile rt) slots NX-2, NX-1
     constexpr int se = Mfma<Real>::kElemLow ? kNX - 6 : kNX - 4;
     constexpr int sg = Mfma<Real>::kElemLow ? kNX - 4 : kNX - 6;
-    const int64_t cum0 = slot_cum(j0);
+    const int64_t cum0 = pt.cum0;
     // Driver increments: the four lane groups hold T tiles x SB steps, so each
     // lane draws one increment per SB steps (lane group g: tile g % T, step
     // g / T of the batch) and the steps read them with lane shuffles.
@@ -405,8 +451,14 @@ __global__ void __launch_bounds__(kBlock) exact_period_kernel(PathArgs<Real> a, 
                 st.pt[c][rt] =
                     ((rt & 1) ? r[kNX - 2] : Real(1)) * ((rt & 2) ? r[kNX - 1] : Real(1));
         }
-        const cptr<Real> kstep = kex + step_base(a.N, a.s, k);
-        exact_slots<Real, T, kNX - 1>(a, st, kstep, cum0, k, j0, offx, lane, dH, xw);
+        const cptr<Real> kstep = kex + pt.base + js * pt.step;
+        // first table chunk of the first coupled slot (NX - 2), when it is live
+        Real pre[4] = {Real(0), Real(0), Real(0), Real(0)};
+        if (kNX - 2 >= j0) {
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt) pre[rt] = kstep[slot_cum(kNX - 2) - cum0 + lane + rt * kWave];
+        }
+        exact_slots<Real, T, kNX - 1>(a, st, kstep, cum0, k, j0, offx, lane, dH, xw, pre);
     }
     if (g == 0) {
 #pragma unroll
@@ -493,7 +545,10 @@ hipError_t launch_exact_t(const lll_plan &p, int64_t n_paths, int64_t path_offse
     const int64_t waves = (n_paths + 16 * T - 1) / (16 * T);
     const dim3 grid(static_cast<unsigned>((waves * kWave + kBlock - 1) / kBlock));
     for (int m = 0; m < p.N && e == hipSuccess; ++m) {
-        hipLaunchKernelGGL((exact_period_kernel<Real, T>), grid, dim3(kBlock), 0, st, a, kc, xs, m);
+        const PeriodTable pt{step_base(p.N, p.s, m * p.s), step_entries(p.N, m),
+                             slot_cum(kNX - p.N + m)};
+        hipLaunchKernelGGL((exact_period_kernel<Real, T>), grid, dim3(kBlock), 0, st, a, kc, xs, m,
+                           pt);
         e = hipGetLastError();
         if (e == hipSuccess) {
             switch (p.nmax) {

@@ -66,22 +66,28 @@ __global__ void __launch_bounds__(256) mix_probe_kernel(
 }
 
 // The matrix-core ceiling of the exact-drift kernel's products: a stream of
-// independent v_mfma_f32_16x16x4f32 (8 accumulators per wavefront, operands
-// in registers, no memory traffic) on 4 wavefronts per SIMD.
+// independent v_mfma_f32_16x16x4f32 (operands in registers, no memory
+// traffic).  A product's accumulator must not be reused before 16 others have
+// issued (8 independent accumulators per wavefront stay near 128 TFLOP/s at
+// two wavefronts per SIMD), so each wavefront cycles through 16, three
+// wavefronts per SIMD.
+constexpr int kMfmaAcc = 16;
+
 __global__ void __launch_bounds__(256) mfma_probe_kernel(float *__restrict__ out, float a0, float b0,
                                                          int iters) {
     typedef float vec4 __attribute__((ext_vector_type(4)));
-    vec4 acc[8];
+    vec4 acc[kMfmaAcc];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) acc[j] = vec4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int j = 0; j < kMfmaAcc; ++j) acc[j] = vec4{0.0f, 0.0f, 0.0f, 0.0f};
     const float a = a0 + threadIdx.x * 1e-7f, b = b0;
     for (int i = 0; i < iters; ++i) {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[j], 0, 0, 0);
+        for (int j = 0; j < kMfmaAcc; ++j)
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[j], 0, 0, 0);
     }
     float s = 0.0f;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) s += (acc[j][0] + acc[j][1]) + (acc[j][2] + acc[j][3]);
+    for (int j = 0; j < kMfmaAcc; ++j) s += (acc[j][0] + acc[j][1]) + (acc[j][2] + acc[j][3]);
     out[blockIdx.x * blockDim.x + threadIdx.x] = s;  // keeps the products live
 }
 
@@ -92,7 +98,7 @@ hipError_t measure_mfma_peak(hipStream_t st, double *tflops) {
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
-    const int blocks = cus * 4, threads = 256, iters = 2048;
+    const int blocks = cus * 3, threads = 256, iters = 1024;
     float *out = nullptr;
     e = hipMalloc(&out, (size_t)blocks * threads * sizeof(float));
     if (e != hipSuccess) return e;
@@ -111,7 +117,8 @@ hipError_t measure_mfma_peak(hipStream_t st, double *tflops) {
         float ms = 0.0f;
         if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
         // 16 x 16 x 4 multiply-adds per instruction and wavefront
-        const double fl = (double)blocks * (threads / kWaveSize) * iters * 8 * (16.0 * 16 * 4 * 2);
+        const double fl =
+            (double)blocks * (threads / kWaveSize) * iters * kMfmaAcc * (16.0 * 16 * 4 * 2);
         if (e == hipSuccess && rep > 0 && ms > 0.0f) best = fmax(best, fl / (ms * 1e-3) / 1e12);
     }
     if (e0) (void)hipEventDestroy(e0);
