@@ -34,7 +34,7 @@ PEAK_FP32 = 157.3e12   # MI355X vector FP32, FLOP/s
 # hash of the kernel sources they were taken on; any other hash reports null.
 # calibrated HBM bytes per launch (profiles/path_kernel_gpu_n20_counters.md), by
 # source hash of the path kernels: a changed kernel reports none
-TRAFFIC_BYTES = {"43fbf0d6f153cb58": {"full": 237235924, "picard": 232727024}}
+TRAFFIC_BYTES = {"8c086270a68b4e70": {"full": 236206005, "picard": 234458368}}
 KERNEL_SOURCES = ["paper_1006_3340_amd/csrc/path_kernel.hpp",
                   "paper_1006_3340_amd/csrc/lll_device.hpp"]
 MLP_SOURCES = ["paper_1006_3340_amd/csrc/mlp_path.hip", "paper_1006_3340_amd/csrc/mlp.hpp",
@@ -44,7 +44,7 @@ MLP_SOURCES = ["paper_1006_3340_amd/csrc/mlp_path.hip", "paper_1006_3340_amd/csr
 # rocprofv3 --pmc figures of the surrogate pricing kernel at 2^20 paths
 # (profiles/mlp_kernels_mlp_n40_mfma_counters.md), by source hash: a changed
 # kernel reports none
-MLP_COUNTERS = {"dfa1400f18a0b1da": {
+MLP_COUNTERS = {"a5ecc42f43f0a7bf": {
     "source": "profiles/mlp_kernels_mlp_n40_mfma_counters.md",
     "mlp_path_kernel_ms": 580.32, "clock_ghz": 2.38,
     "counted_mfma_flop": 2.010e14, "counted_mfma_tflops": 346.4,
@@ -59,7 +59,9 @@ def source_hash(sources) -> str:
     for rel in sources:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
-    h.update(repr((_build.FLAGS, _build.PATH_FLAGS)).encode())
+    # the flags name include directories by absolute path: hash them relative
+    flags = [f.replace(_build.ROOT, "<repo>") for f in _build.FLAGS + _build.PATH_FLAGS]
+    h.update(repr(flags).encode())
     return h.hexdigest()[:16]
 
 
