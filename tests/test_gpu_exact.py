@@ -148,3 +148,26 @@ def test_exact_bench_size_sampled_paths_and_reduction(gpu_lib, oracle_mod):
     B0T = ts.B0_T1 / np.prod(1.0 + ts.delta * ts.L0)
     host_price = ts.delta[:, None] * B0T * pay.mean(axis=0)
     assert np.allclose(got["price"], host_price, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("wl,prec,n", [("gpu_n20", 0, 1 << 16), ("plain_n10", 1, 4096)])
+def test_exact_deterministic_and_split_range(gpu_lib, wl, prec, n):
+    """Repeat runs are bit-identical, and two half-range runs (path offsets 0
+    and n/2, whole wavefronts) give the same per-wavefront partials as the
+    whole run: a path's draws depend only on its global index, its state on
+    nothing shared with other paths."""
+    ts = workloads.WORKLOADS[wl]()
+    with gpu_lib.Plan(ts, precision=prec, max_paths=n) as plan:
+        plan.execute(EXACT, n, seed=7)
+        a, pa = plan.sums(), plan.partials()
+        plan.execute(EXACT, n, seed=7)
+        b, pb = plan.sums(), plan.partials()
+        assert np.array_equal(a, b) and np.array_equal(pa, pb)
+        half = n // 2
+        plan.execute(EXACT, half, seed=7, path_offset=0)
+        p1 = plan.partials()
+        plan.execute(EXACT, half, seed=7, path_offset=half)
+        p2 = plan.partials()
+        assert np.array_equal(np.concatenate([p1, p2]), pa)
+        plan.execute(EXACT, n, seed=8)
+        assert not np.array_equal(plan.sums(), a)
