@@ -647,7 +647,7 @@ def main(argv=None) -> int:
                      "achieved": fl_dom / (ms_dom / 1e3) / 1e12, "peak": PEAK_FP32 / 1e12,
                      "unit": "TFLOP/s", "frac": fl_dom / (ms_dom / 1e3) / PEAK_FP32,
                      "traffic": TRAFFIC_BYTES.get(kernel_hash(), {}).get(dom),
-                     # the quoted FP32 peak counts packed FMAs, which this build
+                     # the quoted FP32 peak counts packed FMAs, which this library
                      # keeps out of its code.  Measured on this GPU: FMAs with
                      # scalar-register operands (the FMA probe) run near one per
                      # lane and cycle (quoted / 2); the recursion's own mix (two

@@ -87,7 +87,7 @@ typedef enum {
     LLL_EMOMENT = -2,      /* exponential-moment condition fails: drift integral diverges */
     LLL_ENOMEM = -3,       /* device allocation failed */
     LLL_EHIP = -4,         /* a HIP runtime call failed (message has the HIP error) */
-    LLL_EUNSUPPORTED = -5, /* valid input outside what this build handles */
+    LLL_EUNSUPPORTED = -5, /* valid input outside what this library implements */
     LLL_ENUMERIC = -6      /* non-finite payoffs were produced */
 } lll_status;
 
