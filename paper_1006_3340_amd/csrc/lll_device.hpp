@@ -36,9 +36,10 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
     return c;
 }
 
-// 24-bit uniform on (0, 1), exact in FP64.
+// 24-bit uniform on (0, 1), exact in FP64: (k + 1/2) 2^-24 = k 2^-24 + 2^-25
+// for the top 24 bits k of the word, one FMA with no rounding.
 __device__ __forceinline__ double uniform24(uint32_t w) {
-    return (static_cast<double>(w >> 8) + 0.5) * (1.0 / 16777216.0);
+    return fma(static_cast<double>(w >> 8), 1.0 / 16777216.0, 1.0 / 33554432.0);
 }
 
 // Per-period constants of the increment: IG mean m = delta dt / gamma, IG shape
