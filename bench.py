@@ -34,7 +34,7 @@ PEAK_FP32 = 157.3e12   # MI355X vector FP32, FLOP/s
 # hash of the kernel sources they were taken on; any other hash reports null.
 # calibrated HBM bytes per launch (profiles/path_kernel_gpu_n20_counters.md), by
 # source hash of the path kernels: a changed kernel reports none
-TRAFFIC_BYTES = {"8c086270a68b4e70": {"full": 236206005, "picard": 234458368}}
+TRAFFIC_BYTES = {"eafa28a651b159c9": {"full": 234428260, "picard": 236654797}}
 KERNEL_SOURCES = ["paper_1006_3340_amd/csrc/path_kernel.hpp",
                   "paper_1006_3340_amd/csrc/lll_device.hpp"]
 MLP_SOURCES = ["paper_1006_3340_amd/csrc/mlp_path.hip", "paper_1006_3340_amd/csrc/mlp.hpp",
@@ -44,11 +44,11 @@ MLP_SOURCES = ["paper_1006_3340_amd/csrc/mlp_path.hip", "paper_1006_3340_amd/csr
 # rocprofv3 --pmc figures of the surrogate pricing kernel at 2^20 paths
 # (profiles/mlp_kernels_mlp_n40_mfma_counters.md), by source hash: a changed
 # kernel reports none
-MLP_COUNTERS = {"a5ecc42f43f0a7bf": {
+MLP_COUNTERS = {"a8e1595fa674f814": {
     "source": "profiles/mlp_kernels_mlp_n40_mfma_counters.md",
-    "mlp_path_kernel_ms": 580.32, "clock_ghz": 2.38,
-    "counted_mfma_flop": 2.010e14, "counted_mfma_tflops": 346.4,
-    "mfma_busy": 0.139, "valu_busy": 0.863, "trans_share_of_valu": 0.193}}
+    "mlp_path_kernel_ms": 577.31, "clock_ghz": 2.38,
+    "counted_mfma_flop": 2.010e+14, "counted_mfma_tflops": 348.2,
+    "mfma_busy": 0.139, "valu_busy": 0.865, "trans_share_of_valu": 0.193}}
 
 
 def source_hash(sources) -> str:
