@@ -9,15 +9,16 @@
 //   1. Philox-4x32-10 words for counter (k, p_lo, p_hi, stream word);
 //   2. the driver increment dH (FP64: subordinator + normal mixture);
 //   3. ell_j = delta_j L_j / (1 + delta_j L_j) of the live rates, from X
-//      (FULL) or from the Picard iterate X1 (PICARD, eq. (bdrift));
+//      (FULL) or of the Picard iterate X1 (PICARD, eq. (bdrift): the kernel
+//      carries that ell itself from step to step, see pred_init);
 //   4. the coupling C_i = sum_q W_q E_{i,q} (prod_{l>i} beta_l(x_q) - 1) by a
 //      suffix recursion over the rates, node by node:
 //          C_i += W_q E_{i,q} R_q,   R_q <- R_q + ell_i E_{i,q} (1 + R_q),
 //      which is the product of eq. (LIBOR-drift-PT) with beta_l = 1 + ell_l E_l
 //      evaluated once for all i (O(N Q) per step instead of O(N^2 Q));
 //      the uniform table entries (E, W E) are wave-uniform scalar operands;
-//   5. X_i += (-kappa_i - C_i) dt + lambda_i dH (PICARD also advances
-//      X1_i += b0_i dt + lambda_i dH; FROZEN advances only X with b0);
+//   5. X_i += (-kappa_i - C_i) dt + lambda_i dH (PICARD also advances its
+//      iterate by b0_i dt + lambda_i dH; FROZEN advances only X with b0);
 //   6. at the end of period m the rate with maturity T_{m+1} fixes: the FP64
 //      payoffs prod_{l>i}(1 + delta_l L_l)(L_i - K)^+ of eq. (caplet) and the
 //      martingale factor are summed across the wavefront (butterfly), and lane
@@ -72,6 +73,18 @@ __device__ __forceinline__ float ell_of(float x, float cinv) {
 }
 __device__ __forceinline__ double ell_of(double x, double cinv) {
     return 1.0 / fma(cinv, exp(-x), 1.0);
+}
+
+// ell after the state moves by d: with L' = L e^d, ell' = delta L' / (1 + delta L')
+// = ell / (ell + (1 - ell) e^{-d}).  PICARD carries the predictor's ell this
+// way instead of its state, which saves one register per rate.
+__device__ __forceinline__ float ell_advance(float ell, float d) {
+    const float e = __expf(-d);
+    return ell * __builtin_amdgcn_rcpf(fmaf(ell, 1.0f - e, e));
+}
+__device__ __forceinline__ double ell_advance(double ell, double d) {
+    const double e = exp(-d);
+    return ell / fma(ell, 1.0 - e, e);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -176,10 +189,21 @@ __device__ __forceinline__ void coupling(const PathArgs<Real> &a, int k, const R
         quad_coupling<Real, NMAX, J0>(a.ew + (size_t)k * kQ * NMAX * 2, ell, C);
 }
 
+// PICARD's predictor (the frozen-drift path, paper Section 3.1) enters the
+// drift only through its ell, so the kernels carry that ell per slot (pred,
+// initialised by pred_init) and move it by each step's frozen-drift
+// increment with ell_advance.  The other schemes leave pred alone.
+template <typename Real, int NMAX, int SCHEME>
+__device__ __forceinline__ void pred_init(const PathArgs<Real> &a, Real (&pred)[NMAX]) {
+#pragma unroll
+    for (int j = 0; j < NMAX; ++j)
+        pred[j] = SCHEME == kPicard ? ell_of(Real(0), a.cinv[j]) : Real(0);
+}
+
 // One Euler step for the live slots J0 .. NMAX-1 (drift and state update).
 template <typename Real, int NMAX, int SCHEME, int J0>
 __device__ __forceinline__ void step(const PathArgs<Real> &a, int k, Real dH, Real (&X)[NMAX],
-                                     Real (&X1)[NMAX]) {
+                                     Real (&pred)[NMAX]) {
     const cptr<Real> lamk = a.lam + (size_t)k * NMAX;
     const cptr<Real> frzk = a.frozen + (size_t)k * NMAX;
     if constexpr (SCHEME == kFrozen) {
@@ -189,7 +213,7 @@ __device__ __forceinline__ void step(const PathArgs<Real> &a, int k, Real dH, Re
         Real ell[NMAX];
 #pragma unroll
         for (int j = J0; j < NMAX; ++j)
-            ell[j] = ell_of(SCHEME == kPicard ? X1[j] : X[j], a.cinv[j]);
+            ell[j] = SCHEME == kPicard ? pred[j] : ell_of(X[j], a.cinv[j]);
         Real C[NMAX];
         coupling<Real, NMAX, SCHEME, J0>(a, k, ell, C);
         const Real dt = a.dt[k];
@@ -198,7 +222,7 @@ __device__ __forceinline__ void step(const PathArgs<Real> &a, int k, Real dH, Re
         for (int j = J0; j < NMAX; ++j) X[j] += fma(lamk[j], dH, fma(-C[j], dt, d0k[j]));
         if constexpr (SCHEME == kPicard) {
 #pragma unroll
-            for (int j = J0; j < NMAX; ++j) X1[j] += fma(lamk[j], dH, frzk[j]);
+            for (int j = J0; j < NMAX; ++j) pred[j] = ell_advance(pred[j], fma(lamk[j], dH, frzk[j]));
         }
     }
 }
@@ -367,13 +391,13 @@ __device__ __forceinline__ void payoff_lds(const PathArgs<Real> &a, int m, int64
 // across the node loop again.
 template <typename Real, int NMAX, int SCHEME, int J0>
 __device__ __forceinline__ void step_lds(const PathArgs<Real> &a, int k, Real dH, Real *xs,
-                                         Real (&X1)[NMAX]) {
+                                         Real (&pred)[NMAX]) {
     const cptr<Real> lamk = a.lam + (size_t)k * NMAX;
     const cptr<Real> frzk = a.frozen + (size_t)k * NMAX;
     Real ell[NMAX];
 #pragma unroll
     for (int j = J0; j < NMAX; ++j)
-        ell[j] = ell_of(SCHEME == kPicard ? X1[j] : xs[j * kBlock], a.cinv[j]);
+        ell[j] = SCHEME == kPicard ? pred[j] : ell_of(xs[j * kBlock], a.cinv[j]);
     __asm__ volatile("" ::: "memory");
     Real C[NMAX];
     coupling<Real, NMAX, SCHEME, J0>(a, k, ell, C);
@@ -383,22 +407,22 @@ __device__ __forceinline__ void step_lds(const PathArgs<Real> &a, int k, Real dH
     for (int j = J0; j < NMAX; ++j) xs[j * kBlock] += fma(lamk[j], dH, fma(-C[j], dt, d0k[j]));
     if constexpr (SCHEME == kPicard) {
 #pragma unroll
-        for (int j = J0; j < NMAX; ++j) X1[j] += fma(lamk[j], dH, frzk[j]);
+        for (int j = J0; j < NMAX; ++j) pred[j] = ell_advance(pred[j], fma(lamk[j], dH, frzk[j]));
     }
 }
 
 template <typename Real, int NMAX, int SCHEME, int... Js>
 __device__ __forceinline__ void dispatch_step_lds(std::integer_sequence<int, Js...>, int j0,
                                                   const PathArgs<Real> &a, int k, Real dH,
-                                                  Real *xs, Real (&X1)[NMAX]) {
-    (void)((j0 == Js ? (step_lds<Real, NMAX, SCHEME, Js>(a, k, dH, xs, X1), 0) : 0) + ...);
+                                                  Real *xs, Real (&pred)[NMAX]) {
+    (void)((j0 == Js ? (step_lds<Real, NMAX, SCHEME, Js>(a, k, dH, xs, pred), 0) : 0) + ...);
 }
 
 template <typename Real, int NMAX, int SCHEME, int... Js>
 __device__ __forceinline__ void dispatch_step(std::integer_sequence<int, Js...>, int j0,
                                               const PathArgs<Real> &a, int k, Real dH,
-                                              Real (&X)[NMAX], Real (&X1)[NMAX]) {
-    (void)((j0 == Js ? (step<Real, NMAX, SCHEME, Js>(a, k, dH, X, X1), 0) : 0) + ...);
+                                              Real (&X)[NMAX], Real (&pred)[NMAX]) {
+    (void)((j0 == Js ? (step<Real, NMAX, SCHEME, Js>(a, k, dH, X, pred), 0) : 0) + ...);
 }
 
 template <typename Real, int NMAX, int PRODUCT, int... Js>
@@ -423,12 +447,10 @@ __device__ __forceinline__ void simulate_lds(const PathArgs<Real> &a, int64_t gi
     const uint32_t p_lo = static_cast<uint32_t>(p);
     const uint32_t p_hi = static_cast<uint32_t>(static_cast<uint64_t>(p) >> 32);
     const bool brownian = a.brownian != 0;
-    Real X1[NMAX];
+    Real pred[NMAX];
+    pred_init<Real, NMAX, SCHEME>(a, pred);
 #pragma unroll
-    for (int j = 0; j < NMAX; ++j) {
-        xs[j * kBlock] = Real(0);
-        X1[j] = Real(0);
-    }
+    for (int j = 0; j < NMAX; ++j) xs[j * kBlock] = Real(0);
     int m = 0, js = 0;
     const int K = a.N * a.s;
     for (int k = 0; k < K; ++k) {
@@ -439,7 +461,7 @@ __device__ __forceinline__ void simulate_lds(const PathArgs<Real> &a, int64_t gi
         const Real dH = static_cast<Real>(increment(w, cst, a.beta, brownian, nullptr));
         const int j0 = a.off + m;
         dispatch_step_lds<Real, NMAX, SCHEME>(std::make_integer_sequence<int, NMAX>{}, j0, a, k, dH,
-                                              xs, X1);
+                                              xs, pred);
         if (++js == a.s) {
             payoff_lds<Real, NMAX, PRODUCT>(a, m, gid, active, xs, j0);
             js = 0;
@@ -473,12 +495,10 @@ __device__ __forceinline__ void simulate(const PathArgs<Real> &a, int64_t gid) {
     const uint32_t p_lo = static_cast<uint32_t>(p);
     const uint32_t p_hi = static_cast<uint32_t>(static_cast<uint64_t>(p) >> 32);
     const bool brownian = a.brownian != 0;
-    Real X[NMAX], X1[NMAX];
+    Real X[NMAX], pred[NMAX];
+    pred_init<Real, NMAX, SCHEME>(a, pred);
 #pragma unroll
-    for (int j = 0; j < NMAX; ++j) {
-        X[j] = Real(0);
-        X1[j] = Real(0);
-    }
+    for (int j = 0; j < NMAX; ++j) X[j] = Real(0);
     int m = 0, js = 0;
     const int K = a.N * a.s;
     for (int k = 0; k < K; ++k) {
@@ -489,7 +509,7 @@ __device__ __forceinline__ void simulate(const PathArgs<Real> &a, int64_t gid) {
         const Real dH = static_cast<Real>(increment(w, cst, a.beta, brownian, nullptr));
         const int j0 = a.off + m;
         dispatch_step<Real, NMAX, SCHEME>(std::make_integer_sequence<int, NMAX>{}, j0, a, k, dH, X,
-                                          X1);
+                                          pred);
         if (++js == a.s) {
             dispatch_payoff<Real, NMAX, PRODUCT>(std::make_integer_sequence<int, NMAX>{}, j0, a, m, gid,
                                         active, X);
