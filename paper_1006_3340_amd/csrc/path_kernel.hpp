@@ -219,10 +219,10 @@ __device__ __forceinline__ void step(const PathArgs<Real> &a, int k, Real dH, Re
         const Real dt = a.dt[k];
         const cptr<Real> d0k = a.drift0 + (size_t)k * NMAX;
 #pragma unroll
-        for (int j = J0; j < NMAX; ++j) X[j] += fma(lamk[j], dH, fma(-C[j], dt, d0k[j]));
-        if constexpr (SCHEME == kPicard) {
-#pragma unroll
-            for (int j = J0; j < NMAX; ++j) pred[j] = ell_advance(pred[j], fma(lamk[j], dH, frzk[j]));
+        for (int j = J0; j < NMAX; ++j) {
+            const Real lam = lamk[j];
+            X[j] += fma(lam, dH, fma(-C[j], dt, d0k[j]));
+            if constexpr (SCHEME == kPicard) pred[j] = ell_advance(pred[j], fma(lam, dH, frzk[j]));
         }
     }
 }
@@ -403,11 +403,13 @@ __device__ __forceinline__ void step_lds(const PathArgs<Real> &a, int k, Real dH
     coupling<Real, NMAX, SCHEME, J0>(a, k, ell, C);
     const Real dt = a.dt[k];
     const cptr<Real> d0k = a.drift0 + (size_t)k * NMAX;
+    // each slot's table entries (lambda, -kappa dt, b0 dt) are used together,
+    // so few of them are live in scalar registers at once
 #pragma unroll
-    for (int j = J0; j < NMAX; ++j) xs[j * kBlock] += fma(lamk[j], dH, fma(-C[j], dt, d0k[j]));
-    if constexpr (SCHEME == kPicard) {
-#pragma unroll
-        for (int j = J0; j < NMAX; ++j) pred[j] = ell_advance(pred[j], fma(lamk[j], dH, frzk[j]));
+    for (int j = J0; j < NMAX; ++j) {
+        const Real lam = lamk[j];
+        xs[j * kBlock] += fma(lam, dH, fma(-C[j], dt, d0k[j]));
+        if constexpr (SCHEME == kPicard) pred[j] = ell_advance(pred[j], fma(lam, dH, frzk[j]));
     }
 }
 
