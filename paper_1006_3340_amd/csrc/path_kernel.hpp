@@ -434,16 +434,26 @@ __device__ __forceinline__ void dispatch_payoff(std::integer_sequence<int, Js...
     (void)((j0 == Js ? (payoff<Real, NMAX, Js, PRODUCT>(a, m, gid, active, X), 0) : 0) + ...);
 }
 
-// The block's LDS state, [slot][thread]: one allocation per kernel that uses it.
+// The block's LDS state, [slot][thread]: one allocation per kernel that uses
+// it, NMAX slots (the batched kernel, whose structures differ in N).
 template <typename Real, int NMAX>
 __device__ __forceinline__ Real *state_lds() {
     __shared__ Real sX[NMAX * kBlock];
     return sX;
 }
 
+// The path kernel's LDS state: rows for the structure's N rates only (slot j
+// in row j - off), sized at launch (N x 256 x 4 B), so that N = 20 in the
+// 24-slot bucket takes 20 KB per block, not 24 KB: 8 blocks per CU instead
+// of 6.  Returns the thread's column, indexed by slot (slots >= off only).
+template <typename Real>
+__device__ __forceinline__ Real *state_lds_dynamic(int off) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char lll_state_dyn[];
+    return reinterpret_cast<Real *>(lll_state_dyn) + threadIdx.x - off * kBlock;
+}
+
 template <typename Real, int NMAX, int SCHEME, int PRODUCT>
-__device__ __forceinline__ void simulate_lds(const PathArgs<Real> &a, int64_t gid) {
-    Real *xs = state_lds<Real, NMAX>() + threadIdx.x;
+__device__ __forceinline__ void simulate_lds(const PathArgs<Real> &a, int64_t gid, Real *xs) {
     const bool active = gid < a.n_paths;
     const int64_t p = a.path_offset + gid;
     const uint32_t p_lo = static_cast<uint32_t>(p);
@@ -452,7 +462,8 @@ __device__ __forceinline__ void simulate_lds(const PathArgs<Real> &a, int64_t gi
     Real pred[NMAX];
     pred_init<Real, NMAX, SCHEME>(a, pred);
 #pragma unroll
-    for (int j = 0; j < NMAX; ++j) xs[j * kBlock] = Real(0);
+    for (int j = 0; j < NMAX; ++j)
+        if (j >= a.off) xs[j * kBlock] = Real(0);
     int m = 0, js = 0;
     const int K = a.N * a.s;
     for (int k = 0; k < K; ++k) {
@@ -486,10 +497,13 @@ constexpr bool kStateInLds = sizeof(Real) == 4 && NMAX >= 24 && SCHEME != kFroze
 // every thread of the block index its own LDS column (threadIdx.x < kBlock).
 // ALLOW_LDS = false keeps the state in registers; PRODUCT is LLL_CAPLETS,
 // LLL_SWAPTIONS or kAnyProduct (see payoff).
-template <typename Real, int NMAX, int SCHEME, bool ALLOW_LDS, int PRODUCT>
+template <typename Real, int NMAX, int SCHEME, bool ALLOW_LDS, int PRODUCT, bool DYN_LDS = false>
 __device__ __forceinline__ void simulate(const PathArgs<Real> &a, int64_t gid) {
     if constexpr (ALLOW_LDS && kStateInLds<Real, NMAX, SCHEME>) {
-        simulate_lds<Real, NMAX, SCHEME, PRODUCT>(a, gid);
+        if constexpr (DYN_LDS)
+            simulate_lds<Real, NMAX, SCHEME, PRODUCT>(a, gid, state_lds_dynamic<Real>(a.off));
+        else
+            simulate_lds<Real, NMAX, SCHEME, PRODUCT>(a, gid, state_lds<Real, NMAX>() + threadIdx.x);
         return;
     }
     const bool active = gid < a.n_paths;
@@ -521,12 +535,14 @@ __device__ __forceinline__ void simulate(const PathArgs<Real> &a, int64_t gid) {
     }
 }
 
+// LDS state (dynamic, launch_scheme sizes it by N) for the wide FP32
+// buckets, registers otherwise.
 template <typename Real, int NMAX, int SCHEME, int PRODUCT>
 __global__ void __launch_bounds__(kBlock) path_kernel(PathArgs<Real> a) {
     const int64_t gid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     const int64_t wave_first = gid - (threadIdx.x % kWave);
     if (wave_first >= a.n_paths) return;  // whole wavefront past the end
-    simulate<Real, NMAX, SCHEME, true, PRODUCT>(a, gid);
+    simulate<Real, NMAX, SCHEME, true, PRODUCT, true>(a, gid);
 }
 
 // Drift of the live rates at step k for given rate vectors (inspection): the
@@ -605,24 +621,26 @@ inline PathArgs<Real> make_args(const lll_plan &p, uint64_t seed, int64_t n_path
     return a;
 }
 
+// Dynamic LDS of path_kernel<Real, NMAX, SCHEME>: the state rows of the N rates.
+template <typename Real, int NMAX, int SCHEME>
+size_t state_lds_bytes(const PathArgs<Real> &a) {
+    return kStateInLds<Real, NMAX, SCHEME> ? size_t(a.N) * kBlock * sizeof(Real) : 0;
+}
+
+template <typename Real, int NMAX, int PRODUCT, int SCHEME>
+void launch_one_scheme(const PathArgs<Real> &a, dim3 grid, hipStream_t st) {
+    const size_t lds = state_lds_bytes<Real, NMAX, SCHEME>(a);
+    hipLaunchKernelGGL((path_kernel<Real, NMAX, SCHEME, PRODUCT>), grid, dim3(kBlock), lds, st, a);
+}
+
 template <typename Real, int NMAX, int PRODUCT>
 void launch_scheme(const PathArgs<Real> &a, int scheme, dim3 grid, hipStream_t st) {
     switch (scheme) {
-        case kFull:
-            hipLaunchKernelGGL((path_kernel<Real, NMAX, kFull, PRODUCT>), grid, dim3(kBlock), 0, st, a);
-            break;
-        case kPicard:
-            hipLaunchKernelGGL((path_kernel<Real, NMAX, kPicard, PRODUCT>), grid, dim3(kBlock), 0, st, a);
-            break;
-        case kFirst:
-            hipLaunchKernelGGL((path_kernel<Real, NMAX, kFirst, PRODUCT>), grid, dim3(kBlock), 0, st, a);
-            break;
-        case kSecond:
-            hipLaunchKernelGGL((path_kernel<Real, NMAX, kSecond, PRODUCT>), grid, dim3(kBlock), 0, st, a);
-            break;
-        default:
-            hipLaunchKernelGGL((path_kernel<Real, NMAX, kFrozen, PRODUCT>), grid, dim3(kBlock), 0, st, a);
-            break;
+        case kFull: launch_one_scheme<Real, NMAX, PRODUCT, kFull>(a, grid, st); break;
+        case kPicard: launch_one_scheme<Real, NMAX, PRODUCT, kPicard>(a, grid, st); break;
+        case kFirst: launch_one_scheme<Real, NMAX, PRODUCT, kFirst>(a, grid, st); break;
+        case kSecond: launch_one_scheme<Real, NMAX, PRODUCT, kSecond>(a, grid, st); break;
+        default: launch_one_scheme<Real, NMAX, PRODUCT, kFrozen>(a, grid, st); break;
     }
 }
 
