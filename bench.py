@@ -34,7 +34,7 @@ PEAK_FP32 = 157.3e12   # MI355X vector FP32, FLOP/s
 # hash of the kernel sources they were taken on; any other hash reports null.
 # calibrated HBM bytes per launch (profiles/path_kernel_gpu_n20_counters.md), by
 # source hash of the path kernels: a changed kernel reports none
-TRAFFIC_BYTES = {"eafa28a651b159c9": {"full": 234428260, "picard": 236654797}}
+TRAFFIC_BYTES = {"29ed60f012486746": {"full": 236491207, "picard": 239016742}}
 KERNEL_SOURCES = ["paper_1006_3340_amd/csrc/path_kernel.hpp",
                   "paper_1006_3340_amd/csrc/lll_device.hpp"]
 MLP_SOURCES = ["paper_1006_3340_amd/csrc/mlp_path.hip", "paper_1006_3340_amd/csrc/mlp.hpp",
@@ -44,11 +44,11 @@ MLP_SOURCES = ["paper_1006_3340_amd/csrc/mlp_path.hip", "paper_1006_3340_amd/csr
 # rocprofv3 --pmc figures of the surrogate pricing kernel at 2^20 paths
 # (profiles/mlp_kernels_mlp_n40_mfma_counters.md), by source hash: a changed
 # kernel reports none
-MLP_COUNTERS = {"a8e1595fa674f814": {
+MLP_COUNTERS = {"2a3cf1df7e3eaea8": {
     "source": "profiles/mlp_kernels_mlp_n40_mfma_counters.md",
-    "mlp_path_kernel_ms": 577.31, "clock_ghz": 2.38,
-    "counted_mfma_flop": 2.010e+14, "counted_mfma_tflops": 348.2,
-    "mfma_busy": 0.139, "valu_busy": 0.865, "trans_share_of_valu": 0.193}}
+    "mlp_path_kernel_ms": 578.71, "clock_ghz": 2.38,
+    "counted_mfma_flop": 2.010e+14, "counted_mfma_tflops": 347.3,
+    "mfma_busy": 0.139, "valu_busy": 0.866, "trans_share_of_valu": 0.193}}
 
 
 def source_hash(sources) -> str:
