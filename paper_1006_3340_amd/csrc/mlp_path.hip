@@ -11,15 +11,18 @@
 // accumulation) for the wavefront's 64 paths at once, as Z^T = W . H^T: the
 // weights are the A operand (LDS, shared by the block), the activations the B
 // operand, the accumulators start from the biases.  Layer 1 reads the BF16
-// state of all rates from a per-wavefront LDS tile written once per step and
-// masks the rates l <= i of rate i's features as it loads them (its bias,
+// states from a per-wavefront LDS tile written once per step with the rates
+// l <= i of the step's first coupled rate i zeroed; the rates are taken in
+// ascending order and each zeroes one more column of the tile (its bias,
 // b1 + the time column x t_k/T_N + rate i's one-hot column, is a per-(step,
 // rate) table).  A lane's accumulator tile holds units 16 mt + 4 g + e of
 // paths 16 nt + c (lane = 16 g + c); with the hidden units of the next layer's
 // K dimension permuted accordingly (perm_unit), those GELU outputs are
 // already that layer's B operand, so the hidden activations never leave the
-// registers.  The output unit reduces the 16 units per lane across the four
-// lane groups.  Nothing is shared between wavefronts inside the step loop.
+// registers.  The output unit (64 -> 1) runs on the matrix cores as well: its
+// FP32 weights split exactly into three BF16 terms (A operand rows 4 g + p),
+// whose products with the BF16 activations are exact and summed in FP32.
+// Nothing is shared between wavefronts inside the step loop.
 //
 // Fallback: a path whose later-rate state leaves the range seen in training
 // (per rate) takes the 64-node quadrature coupling for that rate instead.
@@ -74,6 +77,17 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Term p (0, 1, 2) of the exact split of an FP32 weight into three BF16
+// values, w = hi + mid + lo (each term takes the next 8 significant bits of
+// what the previous ones leave; the differences are exact in FP32).
+__device__ __forceinline__ __bf16 w4_term(float w, int p) {
+    const __bf16 hi = static_cast<__bf16>(w);
+    const float r1 = w - static_cast<float>(hi);
+    const __bf16 mid = static_cast<__bf16>(r1);
+    const __bf16 lo = static_cast<__bf16>(r1 - static_cast<float>(mid));
+    return p == 0 ? hi : p == 1 ? mid : lo;
 }
 
 // Start of a step for the live slots J0..: the trust-box test of the state and
@@ -189,16 +203,18 @@ __device__ __forceinline__ void layer2(const __bf16 *Wp, int lane, const bf16x8 
         }
 }
 
-// Two wavefronts per SIMD (256 registers each, two 63 KiB blocks per CU): left
+// Two wavefronts per SIMD (256 registers each, two 65 KiB blocks per CU): left
 // to itself the compiler takes ~300 registers and one wavefront, which runs
 // the pass 1.6x slower (956 vs 581 ms at 2^20 paths).
 template <int SCHEME>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
 mlp_path_kernel(PathArgs<float> a, MlpArgs g) {
-    // 63 KiB: three padded weight tiles (shared) and one state tile per wavefront
+    // 65 KiB: three padded weight tiles and the output unit's A operand
+    // (shared), one state tile per wavefront
     __shared__ __attribute__((aligned(16))) __bf16 W1p[kHid * kLd];
     __shared__ __attribute__((aligned(16))) __bf16 W2p[kHid * kLd];
     __shared__ __attribute__((aligned(16))) __bf16 W3p[kHid * kLd];
+    __shared__ __attribute__((aligned(16))) __bf16 W4p[16 * kLd];
     __shared__ __attribute__((aligned(16))) __bf16 Ft[kBlock / kWave][kWave * kLd];
     const int tid = threadIdx.x;
     for (int e = tid; e < kHid * kLd; e += kBlock) {
@@ -209,6 +225,11 @@ mlp_path_kernel(PathArgs<float> a, MlpArgs g) {
         W1p[e] = (ks < kSlots && rate >= 0) ? g.wbf[kOffW1 + o * kIn + 1 + rate] : z;
         W2p[e] = (ks < kHid) ? g.wbf[kOffW2 + o * kHid + perm_unit(ks)] : z;
         W3p[e] = (ks < kHid) ? g.wbf[kOffW3 + o * kHid + perm_unit(ks)] : z;
+    }
+    for (int e = tid; e < 16 * kLd; e += kBlock) {
+        const int row = e / kLd, ks = e % kLd;
+        W4p[e] = (ks < kHid && row % 4 < 3) ? w4_term(g.wf[kOffW4 + perm_unit(ks)], row % 4)
+                                            : static_cast<__bf16>(0.0f);
     }
     __syncthreads();  // the only block-wide barrier: the weights are read-only after it
     const int64_t gid = static_cast<int64_t>(blockIdx.x) * kBlock + tid;
@@ -242,13 +263,16 @@ mlp_path_kernel(PathArgs<float> a, MlpArgs g) {
         dispatch_first_order(std::make_integer_sequence<int, kSlots>{}, j0, a, g, k, X, C, oob);
         // the last live slot has no later rate: its coupling stays exactly 0
         if (g.use_net && j0 < kSlots - 1) {
-            // this lane's row of the state tile: BF16 X of slot j at column j
+            // this lane's row of the state tile: BF16 X of slot l at column l for
+            // the rates l > j0 (the features of the first coupled rate), zero
+            // at the other columns
             wave_sync();  // the previous step's reads of the tile are done
 #pragma unroll
             for (int c0 = 0; c0 < kSlots; c0 += 8) {
                 bf16x8 v;
 #pragma unroll
-                for (int e = 0; e < 8; ++e) v[e] = static_cast<__bf16>(X[c0 + e]);
+                for (int e = 0; e < 8; ++e)
+                    v[e] = static_cast<__bf16>(c0 + e > j0 ? X[c0 + e] : 0.0f);
                 *reinterpret_cast<bf16x8 *>(F + lane * kLd + c0) = v;
             }
             *reinterpret_cast<bf16x8 *>(F + lane * kLd + 40) = bf16x8{};
@@ -256,19 +280,11 @@ mlp_path_kernel(PathArgs<float> a, MlpArgs g) {
             *reinterpret_cast<bf16x8 *>(F + lane * kLd + 56) = bf16x8{};
             wave_sync();
             const float *B1k = g.B1 + (size_t)k * kRates * kHid;
-            for (int j = kSlots - 2; j >= j0; --j) {
+            // rates in ascending slot order: after rate j the tile's column j + 1
+            // is zeroed, so rate j + 1 reads exactly the states l > j + 1
+            for (int j = j0; j < kSlots - 1; ++j) {
                 const int r = j - a.off;
-                // features of the rate in slot j: state columns l > j (dword d
-                // of K slice kt holds columns 32 kt + 8 grp + 2 d and + 1)
-                uint32_t mask[2][4];
-#pragma unroll
-                for (int kt = 0; kt < 2; ++kt)
-#pragma unroll
-                    for (int d = 0; d < 4; ++d) {
-                        const int l0 = 32 * kt + 8 * grp + 2 * d;
-                        mask[kt][d] = (l0 > j ? 0x0000FFFFu : 0u) | (l0 + 1 > j ? 0xFFFF0000u : 0u);
-                    }
-                float part[4];
+                float mine = 0.0f;
 #pragma unroll 1
                 for (int np = 0; np < 2; ++np) {
                     bf16x8 B[2][2];
@@ -277,14 +293,9 @@ mlp_path_kernel(PathArgs<float> a, MlpArgs g) {
                     for (int t = 0; t < 2; ++t) {
                         const int nt = 2 * np + t;
 #pragma unroll
-                        for (int kt = 0; kt < 2; ++kt) {
-                            bf16x8 f = *reinterpret_cast<const bf16x8 *>(
+                        for (int kt = 0; kt < 2; ++kt)
+                            B[t][kt] = *reinterpret_cast<const bf16x8 *>(
                                 F + (16 * nt + lane % 16) * kLd + 32 * kt + 8 * grp);
-                            uint32_t *u = reinterpret_cast<uint32_t *>(&f);
-#pragma unroll
-                            for (int d = 0; d < 4; ++d) u[d] &= mask[kt][d];
-                            B[t][kt] = f;
-                        }
                         bias_init(B1k + r * kHid, grp, acc[t]);
                     }
                     layer2(W1p, lane, B, acc);
@@ -300,32 +311,31 @@ mlp_path_kernel(PathArgs<float> a, MlpArgs g) {
                         bias_init(g.wfv + kOffB3, grp, acc[t]);
                     }
                     layer2(W3p, lane, B, acc);
-                    // output unit: this lane's 16 units of its column tile
+#pragma unroll
+                    for (int t = 0; t < 2; ++t) activate(acc[t], B[t]);
+                    // output unit on the matrix cores: every lane group's rows
+                    // 4 g + p hold term p of w4, so element p of a lane's
+                    // accumulator is term p's dot product with the 64 units of
+                    // path 16 nt + c; lane 16 grp + c keeps column tile grp
                     __asm__ volatile("" ::: "memory");
+                    floatx4 out[2] = {floatx4{}, floatx4{}};
 #pragma unroll
-                    for (int t = 0; t < 2; ++t) {
-                        float sum = 0.0f;
+                    for (int kt = 0; kt < 2; ++kt) {
+                        const bf16x8 w = *reinterpret_cast<const bf16x8 *>(
+                            W4p + (lane % 16) * kLd + 32 * kt + 8 * grp);
 #pragma unroll
-                        for (int mt = 0; mt < 4; ++mt) {
-                            const floatx4 w4 =
-                                *reinterpret_cast<const floatx4 *>(g.wfv + kOffW4 + 16 * mt + 4 * grp);
-#pragma unroll
-                            for (int e = 0; e < 4; ++e)
-                                sum = fmaf(w4[e], static_cast<float>(static_cast<__bf16>(gelu(acc[t][mt][e]))), sum);
-                        }
-                        part[2 * np + t] = sum;
+                        for (int t = 0; t < 2; ++t) out[t] = mfma16(w, B[t][kt], out[t]);
                     }
-                }
-                // sum over the four lane groups; lane 16 grp + c keeps column tile grp
 #pragma unroll
-                for (int nt = 0; nt < 4; ++nt) {
-                    part[nt] += __shfl_xor(part[nt], 16, kWave);
-                    part[nt] += __shfl_xor(part[nt], 32, kWave);
+                    for (int t = 0; t < 2; ++t)
+                        mine = (grp == 2 * np + t) ? (out[t][0] + out[t][1]) + out[t][2] : mine;
                 }
-                const float mine = grp == 0 ? part[0] : grp == 1 ? part[1] : grp == 2 ? part[2] : part[3];
                 const float sy = g.sigma * (g.wf[kOffB4] + mine);
 #pragma unroll
                 for (int jj = 0; jj < kSlots - 1; ++jj) C[jj] += (jj == j) ? sy : 0.0f;
+                // the next rate's features leave out this lane's state at column j + 1
+                F[lane * kLd + j + 1] = static_cast<__bf16>(0.0f);
+                wave_sync();
             }
         }
         const bool need_quad = judge || __any((oob >> (j0 + 1)) != 0);
