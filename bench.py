@@ -44,11 +44,11 @@ MLP_SOURCES = ["paper_1006_3340_amd/csrc/mlp_path.hip", "paper_1006_3340_amd/csr
 # rocprofv3 --pmc figures of the surrogate pricing kernel at 2^20 paths
 # (profiles/mlp_kernels_mlp_n40_mfma_counters.md), by source hash: a changed
 # kernel reports none
-MLP_COUNTERS = {"2a3cf1df7e3eaea8": {
+MLP_COUNTERS = {"a1076cf3558cc8f7": {
     "source": "profiles/mlp_kernels_mlp_n40_mfma_counters.md",
-    "mlp_path_kernel_ms": 578.71, "clock_ghz": 2.38,
-    "counted_mfma_flop": 2.010e+14, "counted_mfma_tflops": 347.3,
-    "mfma_busy": 0.139, "valu_busy": 0.866, "trans_share_of_valu": 0.193}}
+    "mlp_path_kernel_ms": 524.64, "clock_ghz": 2.37,
+    "counted_mfma_flop": 2.178e+14, "counted_mfma_tflops": 415.1,
+    "mfma_busy": 0.167, "valu_busy": 0.854, "trans_share_of_valu": 0.221}}
 
 
 def source_hash(sources) -> str:
