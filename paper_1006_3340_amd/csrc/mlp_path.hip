@@ -49,8 +49,6 @@ constexpr int kSlots = kRates;  // the surrogate runs in the 40-slot bucket
 constexpr int kNStat = 8;
 constexpr int kLd = 72;         // padded row length (BF16) of the LDS tiles
 
-typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-
 struct MlpArgs {
     cptr<float> wf;     // FP32 parameter vector (biases, w4, b4)
     const float *wfv;   // the same, for per-lane loads
@@ -204,8 +202,8 @@ __device__ __forceinline__ void layer2(const __bf16 *Wp, int lane, const bf16x8 
 }
 
 // Two wavefronts per SIMD (256 registers each, two 65 KiB blocks per CU): left
-// to itself the compiler takes ~300 registers and one wavefront, which runs
-// the pass 1.6x slower (956 vs 581 ms at 2^20 paths).
+// to itself the compiler takes ~300 registers and one wavefront per SIMD,
+// which ran the pass 1.6x slower at 2^20 paths.
 template <int SCHEME>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
 mlp_path_kernel(PathArgs<float> a, MlpArgs g) {
