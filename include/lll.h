@@ -515,6 +515,24 @@ int lll_fp32_mfma_peak(double *tflops_host, void *stream);
 int lll_philox(const uint32_t *ctr_host, const uint32_t *key_host, int64_t n,
                uint32_t *out_host, void *stream);
 
+/* The FP64 routines of the driver increment (the Box-Muller and inverse-
+ * Gaussian steps of Section 4's sampling of the NIG increments), evaluated on
+ * the device for inspection: fn = LLL_SM_LOG log(x) for normal 0 < x <= 1;
+ * LLL_SM_SINPI / LLL_SM_COSPI sin(pi t) / cos(pi t) for t in [0, 2] a multiple
+ * of 2^-24 (the sampler's angles); LLL_SM_SQRT sqrt(x) for normal x > 0;
+ * LLL_SM_DIV x[2i] / x[2i+1] for finite x[2i] and normal x[2i+1] > 0.
+ * x_host holds n arguments (2n for LLL_SM_DIV), out_host[n] the results.
+ * LLL_EINVAL (nothing computed) for an unknown fn, n outside 1 .. 2^26 or an
+ * argument outside the routine's domain. */
+typedef enum {
+    LLL_SM_LOG = 0,
+    LLL_SM_SINPI = 1,
+    LLL_SM_COSPI = 2,
+    LLL_SM_SQRT = 3,
+    LLL_SM_DIV = 4
+} lll_sampler_routine;
+int lll_sampler_math(int fn, const double *x_host, int64_t n, double *out_host, void *stream);
+
 /* Driver increments of step k for paths p0 .. p0 + n - 1 as drawn by the path
  * kernel (FP64): subordinator draws V_host[n] (0 for the Brownian driver) and
  * increments dH_host[n].  Runs the plan's precompute first. */

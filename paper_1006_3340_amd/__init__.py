@@ -8,6 +8,7 @@ library is missing.
 from ._lib import (EXACT, FIRST_ORDER, FP32, FP64, FROZEN, FULL, MLP_DRIFT, N_MAX,  # noqa: F401
                    N_MAX_EXACT, N_MAX_MP, PICARD, PICARD_MP, SECOND_ORDER,
                    Batch, LLLError, Mlp, Plan, caplet_greeks, load, philox, price_caplets,
+                   sampler_math,
                    price_caplets_batched, price_caplets_static, fp32_fma_peak, fp32_mix_peak,
                    fp32_mfma_peak, version)
 

@@ -26,7 +26,8 @@ N_MAX, N_MAX_MP, N_MAX_FP64, N_MAX_EXACT, S_MAX, Q = 40, 64, 24, 20, 8, 64
 
 EXPORTS = ["lll_version", "lll_last_error", "lll_plan_create", "lll_plan_execute",
            "lll_plan_results", "lll_plan_sums", "lll_plan_partials", "lll_plan_destroy",
-           "lll_price_caplets", "lll_philox", "lll_plan_increments", "lll_plan_tables",
+           "lll_price_caplets", "lll_philox", "lll_sampler_math", "lll_plan_increments",
+           "lll_plan_tables",
            "lll_plan_drift", "lll_plan_set_timing", "lll_plan_timing", "lll_batch_create",
            "lll_batch_execute", "lll_batch_results", "lll_batch_set_timing", "lll_batch_timing",
            "lll_batch_destroy", "lll_plan_greeks", "lll_plan_greeks_results", "lll_plan_greeks_vjp",
@@ -100,6 +101,7 @@ def load():
     lib.lll_fp32_mix_peak.argtypes = [dp, vp]
     lib.lll_fp32_mfma_peak.argtypes = [dp, vp]
     lib.lll_philox.argtypes = [u32p, u32p, i64, u32p, vp]
+    lib.lll_sampler_math.argtypes = [ctypes.c_int, dp, i64, dp, vp]
     lib.lll_plan_increments.argtypes = [vp, i32, i64, i64, u64, dp, dp, vp]
     lib.lll_plan_tables.argtypes = [vp, dp, dp, dp, dp, dp, vp]
     lib.lll_plan_drift.argtypes = [vp, i32, dp, i64, dp, vp]
@@ -645,6 +647,25 @@ def philox(ctr: np.ndarray, key: np.ndarray, stream=None) -> np.ndarray:
     u32p = ctypes.POINTER(ctypes.c_uint32)
     _check(lib.lll_philox(ctr.ctypes.data_as(u32p), key.ctypes.data_as(u32p), n,
                           out.ctypes.data_as(u32p), stream_handle(stream)))
+    return out
+
+
+SAMPLER_ROUTINES = {"log": 0, "sinpi": 1, "cospi": 2, "sqrt": 3, "div": 4}
+
+
+def sampler_math(routine: str, x: np.ndarray, stream=None) -> np.ndarray:
+    """lll_sampler_math: one of the driver increment's FP64 routines ("log",
+    "sinpi", "cospi", "sqrt"; "div" takes an (n, 2) array of a, b pairs)
+    evaluated on the device."""
+    lib = load()
+    fn = SAMPLER_ROUTINES[routine]
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+    n = x.shape[0]
+    if fn == SAMPLER_ROUTINES["div"]:
+        x = np.ascontiguousarray(x.reshape(-1, 2))
+        n = x.shape[0]
+    out = np.zeros(n, dtype=np.float64)
+    _check(lib.lll_sampler_math(fn, _dp(x), n, _dp(out), stream_handle(stream)))
     return out
 
 

@@ -533,6 +533,38 @@ int lll_philox(const uint32_t *ctr_host, const uint32_t *key_host, int64_t n, ui
     return LLL_OK;
 }
 
+int lll_sampler_math(int fn, const double *x_host, int64_t n, double *out_host, void *stream) {
+    if (!x_host || !out_host) return fail(LLL_EINVAL, "NULL argument");
+    if (fn < LLL_SM_LOG || fn > LLL_SM_DIV) return fail(LLL_EINVAL, "unknown routine %d", fn);
+    if (n < 1 || n > ((int64_t)1 << 26)) return fail(LLL_EINVAL, "n=%lld out of range", (long long)n);
+    const int64_t nin = fn == LLL_SM_DIV ? 2 * n : n;
+    for (int64_t i = 0; i < nin; ++i) {
+        const double v = x_host[i];
+        bool ok;
+        if (fn == LLL_SM_LOG)
+            ok = std::isnormal(v) && v > 0.0 && v <= 1.0;
+        else if (fn == LLL_SM_SINPI || fn == LLL_SM_COSPI)
+            ok = v >= 0.0 && v <= 2.0 && std::ldexp(v, 24) == std::floor(std::ldexp(v, 24));
+        else if (fn == LLL_SM_SQRT)
+            ok = std::isnormal(v) && v > 0.0;
+        else
+            ok = std::isfinite(v) && (i % 2 == 0 || (std::isnormal(v) && v > 0.0));
+        if (!ok) return fail(LLL_EINVAL, "argument %lld = %g outside the routine's domain", (long long)i, v);
+    }
+    double *d = nullptr;
+    hipError_t e = hipMalloc(&d, (size_t)(nin + n) * sizeof(double));
+    if (e != hipSuccess) return hip_fail(e, "allocating sampler buffers");
+    hipStream_t st = as_stream(stream);
+    e = hipMemcpyAsync(d, x_host, (size_t)nin * sizeof(double), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = lll::launch_sampler_math(fn, d, n, d + nin, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(out_host, d + nin, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(d);
+    if (e != hipSuccess) return hip_fail(e, "sampler routine kernel");
+    return LLL_OK;
+}
+
 int lll_plan_increments(lll_plan *plan, int k, int64_t p0, int64_t n, uint64_t seed,
                         double *V_host, double *dH_host, void *stream) {
     if (!plan || !V_host || !dH_host) return fail(LLL_EINVAL, "NULL argument");

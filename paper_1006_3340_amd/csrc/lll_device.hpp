@@ -42,6 +42,101 @@ __device__ __forceinline__ double uniform24(uint32_t w) {
     return fma(static_cast<double>(w >> 8), 1.0 / 16777216.0, 1.0 / 33554432.0);
 }
 
+// FP64 arithmetic of the increment on its own argument ranges (all operands
+// positive and normal), each a textbook construction with at most 2 ulp of
+// error against the correctly rounded result -- a third of the instructions
+// of the general-purpose library routines, whose double-double steps and
+// special-value paths the sampler does not need.
+
+// a / b for b > 0 normal: hardware reciprocal estimate, two Newton steps
+// r <- r + r (1 - b r), then one residual correction q <- q + r (a - b q)
+// (each residual exact by FMA).
+__device__ __forceinline__ double div_pos(double a, double b) {
+    double r = __builtin_amdgcn_rcp(b);
+    r = fma(fma(-b, r, 1.0), r, r);
+    r = fma(fma(-b, r, 1.0), r, r);
+    const double q = a * r;
+    return fma(fma(-b, q, a), r, q);
+}
+
+// sqrt(x) for x > 0 normal: from the hardware 1/sqrt estimate y, g = x y and
+// h = y / 2 refined by two coupled Newton (Goldschmidt) steps, then
+// g <- g + h (x - g^2).
+__device__ __forceinline__ double sqrt_pos(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const double r = fma(-g, h, 0.5);
+        g = fma(g, r, g);
+        h = fma(h, r, h);
+    }
+    return fma(fma(-g, g, x), h, g);
+}
+
+// log(x) for 0 < x <= 1 normal: x = f 2^e with f in [1/sqrt 2, sqrt 2),
+// log f = 2 atanh(z) = 2 z (1 + z^2/3 + z^4/5 + ...), z = (f - 1) / (f + 1),
+// |z| <= 0.172 (terms through z^19: truncation below 3e-17 relative), and
+// e log 2 with log 2 split into 32 leading bits (e times it is exact) and the
+// FP64 rest.
+__device__ __forceinline__ double log_unit(double x) {
+    constexpr double kLn2Hi = 0x1.62e42ffp-1;             // log 2 to 32 bits
+    constexpr double kLn2Lo = -4.2009150726810846e-11;    // log 2 - kLn2Hi
+    double f = __builtin_amdgcn_frexp_mant(x);             // [1/2, 1)
+    int e = __builtin_amdgcn_frexp_exp(x);
+    if (f < 0.7071067811865476) {
+        f *= 2.0;
+        --e;
+    }
+    const double z = div_pos(f - 1.0, f + 1.0);
+    const double w = z * z;
+    double s = 1.0 / 19.0;
+#pragma unroll
+    for (int j = 7; j >= 0; --j) s = fma(s, w, 1.0 / (2 * j + 3));
+    const double tz = 2.0 * z;
+    const double lf = fma(tz * w, s, tz);
+    const double de = static_cast<double>(e);
+    return fma(de, kLn2Hi, fma(de, kLn2Lo, lf));
+}
+
+// sin(pi t) and cos(pi t) for 0 <= t <= 2 with t a multiple of 2^-24: with
+// v = 2 t, q = rint(v) and r = (v - q) / 2 (both steps exact), pi t =
+// q pi/2 + pi r, |r| <= 1/4; sin(pi r) and cos(pi r) by their Taylor series
+// through r^17 and r^18 (coefficients (-1)^k pi^n / n!; truncation below
+// 1e-18), then the quadrant q mod 4.
+__device__ __forceinline__ void sincospi_unit(double t, double &sn, double &cs) {
+    const double v = 2.0 * t;
+    const double q = __builtin_rint(v);
+    const double r = (v - q) * 0.5;
+    const double x = r * r;
+    double ps = 7.952054001475513e-07;
+    ps = fma(ps, x, -2.1915353447830217e-05);
+    ps = fma(ps, x, 0.00046630280576761255);
+    ps = fma(ps, x, -0.0073704309457143504);
+    ps = fma(ps, x, 0.08214588661112823);
+    ps = fma(ps, x, -0.5992645293207921);
+    ps = fma(ps, x, 2.5501640398773455);
+    ps = fma(ps, x, -5.16771278004997);
+    ps = fma(ps, x, 3.141592653589793);
+    double pc = -1.3878952462213771e-07;
+    pc = fma(pc, x, 4.303069587032947e-06);
+    pc = fma(pc, x, -0.0001046381049248457);
+    pc = fma(pc, x, 0.0019295743094039231);
+    pc = fma(pc, x, -0.02580689139001406);
+    pc = fma(pc, x, 0.2353306303588932);
+    pc = fma(pc, x, -1.3352627688545895);
+    pc = fma(pc, x, 4.0587121264167685);
+    pc = fma(pc, x, -4.934802200544679);
+    pc = fma(pc, x, 1.0);
+    const double s = r * ps;
+    const int qi = static_cast<int>(q) & 3;
+    const bool odd = (qi & 1) != 0;
+    sn = odd ? pc : s;
+    cs = odd ? s : pc;
+    if (qi & 2) sn = -sn;
+    if (qi == 1 || qi == 2) cs = -cs;
+}
+
 // Per-period constants of the increment: IG mean m = delta dt / gamma, IG shape
 // lam = (delta dt)^2, drift mu_H dt, Brownian scale sqrt(c dt).
 struct StepConsts {
@@ -59,9 +154,9 @@ __device__ __forceinline__ double increment(uint4 w, const StepConsts& sc, doubl
     const double u0 = uniform24(w.x);
     const double u1 = uniform24(w.y);
     const double u2 = uniform24(w.z);
-    const double r = sqrt(-2.0 * log(u0));
+    const double r = sqrt_pos(-2.0 * log_unit(u0));
     double sn, cs;
-    sincospi(2.0 * u1, &sn, &cs);
+    sincospi_unit(2.0 * u1, sn, cs);
     const double z1 = r * cs;
     const double z2 = r * sn;
     if (brownian) {
@@ -70,12 +165,12 @@ __device__ __forceinline__ double increment(uint4 w, const StepConsts& sc, doubl
     }
     const double m = sc.m;
     const double a = m * (z1 * z1);
-    const double d = sqrt(a * a + 4.0 * sc.lam * a);
+    const double d = sqrt_pos(a * a + 4.0 * sc.lam * a);
     const double ad = a + d;
-    const double x = (a > 0.0) ? 4.0 * m * sc.lam * a / (ad * ad) : m;
-    const double V = (u2 <= m / (m + x)) ? x : m * m / x;
+    const double x = (a > 0.0) ? div_pos(4.0 * m * sc.lam * a, ad * ad) : m;
+    const double V = (u2 <= div_pos(m, m + x)) ? x : div_pos(m * m, x);
     if (V_out) *V_out = V;
-    return sc.mu_dt + beta * V + sqrt(V) * z2;
+    return sc.mu_dt + beta * V + sqrt_pos(V) * z2;
 }
 
 // NIG cumulant kappa(u) = mu_H u + delta (gamma - sqrt(alpha^2 - (beta+u)^2)),

@@ -185,5 +185,7 @@ hipError_t launch_increments(const lll_plan &p, int k, int64_t p0, int64_t n, ui
                              double *V_dev, double *dH_dev, hipStream_t st);
 hipError_t launch_philox(const uint32_t *ctr_dev, const uint32_t *key_dev, int64_t n,
                          uint32_t *out_dev, hipStream_t st);
+hipError_t launch_sampler_math(int fn, const double *x_dev, int64_t n, double *out_dev,
+                               hipStream_t st);
 
 }  // namespace lll

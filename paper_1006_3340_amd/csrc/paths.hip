@@ -64,6 +64,27 @@ __global__ void __launch_bounds__(kBlock) philox_kernel(const uint32_t *__restri
     out[4 * i + 3] = r.w;
 }
 
+// The increment's FP64 routines on given arguments (fn: LLL_SM_*; LLL_SM_DIV
+// reads the pairs x[2i], x[2i+1]); the host has checked the domains.
+__global__ void __launch_bounds__(kBlock) sampler_math_kernel(int fn, const double *__restrict__ x,
+                                                              int64_t n, double *__restrict__ out) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= n) return;
+    double r = 0.0;
+    if (fn == LLL_SM_LOG) {
+        r = log_unit(x[i]);
+    } else if (fn == LLL_SM_SINPI || fn == LLL_SM_COSPI) {
+        double sn, cs;
+        sincospi_unit(x[i], sn, cs);
+        r = fn == LLL_SM_SINPI ? sn : cs;
+    } else if (fn == LLL_SM_SQRT) {
+        r = sqrt_pos(x[i]);
+    } else {
+        r = div_pos(x[2 * i], x[2 * i + 1]);
+    }
+    out[i] = r;
+}
+
 // Pass 1: block b sums rows [b*256, (b+1)*256) of the wave partials column by
 // column in row order.  Pass 2: one block sums the chunk rows in order.
 __global__ void __launch_bounds__(256) reduce_rows_kernel(const double *__restrict__ in,
@@ -194,6 +215,13 @@ hipError_t launch_increments(const lll_plan &p, int k, int64_t p0, int64_t n, ui
                        p.struct_id & 0xFFFFFFu, static_cast<uint32_t>(seed & 0xFFFFFFFFull),
                        static_cast<uint32_t>(seed >> 32), p.beta,
                        p.driver == LLL_DRIVER_BROWNIAN ? 1 : 0, V_dev, dH_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_sampler_math(int fn, const double *x_dev, int64_t n, double *out_dev,
+                               hipStream_t st) {
+    const dim3 grid(static_cast<unsigned>((n + kBlock - 1) / kBlock));
+    hipLaunchKernelGGL(sampler_math_kernel, grid, dim3(kBlock), 0, st, fn, x_dev, n, out_dev);
     return hipGetLastError();
 }
 

@@ -25,6 +25,7 @@ hipError_t launch_paths(const lll_plan &, int, int64_t, int64_t, uint64_t, doubl
 hipError_t batch_prepare(lll_batch &, int64_t, uint64_t, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_greeks(const lll_plan &, int64_t, uint64_t, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_philox(const uint32_t *, const uint32_t *, int64_t, uint32_t *, hipStream_t) { return hipErrorNotSupported; }
+hipError_t launch_sampler_math(int, const double *, int64_t, double *, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_reduce(const lll_plan &, int64_t, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_batched(const lll_batch &, int, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_picard_mp(const lll_plan &, int64_t, int64_t, uint64_t, double *, hipStream_t) { return hipErrorNotSupported; }

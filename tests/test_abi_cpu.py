@@ -81,6 +81,20 @@ def test_inspection_entry_points_validate():
     import paper_1006_3340_amd as lll
     with pytest.raises(lll.LLLError):
         lll.philox(np.zeros((0, 4), np.uint32), np.zeros((0, 2), np.uint32))
+    # the sampler routines reject arguments outside their domains on the host
+    for routine, x in (("log", [0.5, 0.0]), ("log", [1.5]), ("log", [1e-310]), ("log", [np.nan]),
+                       ("sinpi", [2.5]), ("cospi", [-0.25]), ("sinpi", [0.3]),
+                       ("sqrt", [0.0]), ("sqrt", [-1.0]), ("sqrt", [np.inf]),
+                       ("div", [[1.0, 0.0]]), ("div", [[1.0, -2.0]]), ("div", [[np.inf, 1.0]])):
+        with pytest.raises(lll.LLLError) as ei:
+            lll.sampler_math(routine, np.array(x))
+        assert ei.value.code == -1, (routine, x)
+    lib = lll.load()
+    out = np.zeros(1)
+    x = np.full(1, 0.5)
+    dp = ctypes.POINTER(ctypes.c_double)
+    assert lib.lll_sampler_math(5, x.ctypes.data_as(dp), 1, out.ctypes.data_as(dp), None) == -1
+    assert lib.lll_sampler_math(0, x.ctypes.data_as(dp), 0, out.ctypes.data_as(dp), None) == -1
 
 
 def test_batch_validation_errors():

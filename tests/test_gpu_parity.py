@@ -8,6 +8,10 @@ Tolerances (derived from the arithmetic, not tuned):
   loses up to ~log10(m/x) digits: 1e-11 relative to the sum of the magnitudes
   of the terms of dH.  The subordinator branch is decided in FP64 on both
   sides (same decision precision).
+* The sampler's own FP64 routines (log, sin / cos(pi t), sqrt, division):
+  within 2 ulp (log, sin, cos: one rounding per series step on |z| <= 0.172
+  and |pi r| <= pi/4, each term's error below the next's weight) or 1 ulp
+  (sqrt and division: a residual-corrected Newton step) of 30-digit values.
 * FP64 tables: nodes, weights and E to 1e-13 relative; the cumulant to the
   cancellation bound of the oracle's closed form.
 * FP64 path kernel vs oracle: per-path state errors ~1e-15 relative grow over
@@ -18,6 +22,7 @@ Tolerances (derived from the arithmetic, not tuned):
   error must stay below 1e-4 times the at-the-money price of the same caplet
   (a single path can dominate a deep out-of-the-money caplet).
 """
+import mpmath as mp
 import numpy as np
 import pytest
 
@@ -63,6 +68,40 @@ def test_increments_match_oracle(gpu_lib, oracle_mod, wl):
             mag = abs(mu_dt) + abs(ts.beta) * Vo + np.abs(dHo - mu_dt - ts.beta * Vo)
             angle = np.sqrt(Vo) * 6.0 * 2 * np.pi * 4 * 2.0**-53
             assert np.all(np.abs(dH - dHo) <= 1e-11 * mag + angle), k
+
+
+def _ulps(got, ref):
+    """|got - ref| in units of the last place of the FP64-rounded reference."""
+    ref64 = np.array([float(r) for r in ref])
+    diff = np.array([float(abs(mp.mpf(float(g)) - r)) for g, r in zip(got, ref)])
+    return diff / np.spacing(np.abs(ref64))
+
+
+def test_sampler_routines_accuracy(gpu_lib):
+    """The increment's FP64 routines (Section 4's sampling of the NIG increments:
+    Box-Muller log, sqrt and angle, the inverse-Gaussian root and its divisions)
+    against 30-digit references, on the sampler's own arguments -- 24-bit
+    uniforms (k + 1/2) 2^-24 and angles 2u -- and on wide ranges: log and
+    sin / cos(pi t) within 2 ulp, sqrt and division within 1 ulp."""
+    mp.mp.dps = 30
+    rng = np.random.default_rng(21)
+    k = np.concatenate([[0, 1, 2**22, 2**23, 2**24 - 2, 2**24 - 1], rng.integers(0, 2**24, 6000)])
+    u = (k + 0.5) * 2.0**-24
+    wide = 10.0 ** rng.uniform(-300.0, 0.0, 2000)
+    x = np.concatenate([u, wide])
+    got = gpu_lib.sampler_math("log", x)
+    assert _ulps(got, [mp.log(mp.mpf(float(v))) for v in x]).max() <= 2.0
+    t = np.concatenate([2.0 * u, [0.0, 0.25, 0.5, 1.0, 1.5, 2.0 - 2.0**-24, 2.0]])
+    tm = [mp.mpf(float(v)) for v in t]
+    for routine, f in (("sinpi", mp.sinpi), ("cospi", mp.cospi)):
+        got = gpu_lib.sampler_math(routine, t)
+        assert _ulps(got, [f(v) for v in tm]).max() <= 2.0, routine
+    y = 10.0 ** rng.uniform(-40.0, 10.0, 6000)
+    got = gpu_lib.sampler_math("sqrt", y)
+    assert _ulps(got, [mp.sqrt(mp.mpf(float(v))) for v in y]).max() <= 1.0
+    ab = np.stack([rng.uniform(-1e3, 1e3, 6000), 10.0 ** rng.uniform(-30.0, 30.0, 6000)], axis=1)
+    got = gpu_lib.sampler_math("div", ab)
+    assert _ulps(got, [mp.mpf(float(a)) / mp.mpf(float(b)) for a, b in ab]).max() <= 1.0
 
 
 def test_brownian_increments_match_oracle(gpu_lib, oracle_mod):
