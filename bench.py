@@ -34,7 +34,7 @@ PEAK_FP32 = 157.3e12   # MI355X vector FP32, FLOP/s
 # hash of the kernel sources they were taken on; any other hash reports null.
 # calibrated HBM bytes per launch (profiles/path_kernel_gpu_n20_counters.md), by
 # source hash of the path kernels: a changed kernel reports none
-TRAFFIC_BYTES = {"29ed60f012486746": {"full": 236491207, "picard": 239016742}}
+TRAFFIC_BYTES = {"8b055bc0117f2106": {"full": 226828266, "picard": 233526831}}
 KERNEL_SOURCES = ["paper_1006_3340_amd/csrc/path_kernel.hpp",
                   "paper_1006_3340_amd/csrc/lll_device.hpp"]
 MLP_SOURCES = ["paper_1006_3340_amd/csrc/mlp_path.hip", "paper_1006_3340_amd/csrc/mlp.hpp",
@@ -44,11 +44,11 @@ MLP_SOURCES = ["paper_1006_3340_amd/csrc/mlp_path.hip", "paper_1006_3340_amd/csr
 # rocprofv3 --pmc figures of the surrogate pricing kernel at 2^20 paths
 # (profiles/mlp_kernels_mlp_n40_mfma_counters.md), by source hash: a changed
 # kernel reports none
-MLP_COUNTERS = {"5ceeb77243bee01d": {
+MLP_COUNTERS = {"355912e492cb5187": {
     "source": "profiles/mlp_kernels_mlp_n40_mfma_counters.md",
-    "mlp_path_kernel_ms": 524.64, "clock_ghz": 2.37,
+    "mlp_path_kernel_ms": 524.53, "clock_ghz": 2.38,
     "counted_mfma_flop": 2.178e+14, "counted_mfma_tflops": 415.1,
-    "mfma_busy": 0.167, "valu_busy": 0.854, "trans_share_of_valu": 0.221}}
+    "mfma_busy": 0.166, "valu_busy": 0.851, "trans_share_of_valu": 0.222}}
 
 
 def source_hash(sources) -> str:
