@@ -34,7 +34,7 @@ PEAK_FP32 = 157.3e12   # MI355X vector FP32, FLOP/s
 # hash of the kernel sources they were taken on; any other hash reports null.
 # calibrated HBM bytes per launch (profiles/path_kernel_gpu_n20_counters.md), by
 # source hash of the path kernels: a changed kernel reports none
-TRAFFIC_BYTES = {"8b055bc0117f2106": {"full": 226828266, "picard": 233526831}}
+TRAFFIC_BYTES = {"92e05cbf6a5b5222": {"full": 146993080, "picard": 166064311}}
 KERNEL_SOURCES = ["paper_1006_3340_amd/csrc/path_kernel.hpp",
                   "paper_1006_3340_amd/csrc/lll_device.hpp"]
 MLP_SOURCES = ["paper_1006_3340_amd/csrc/mlp_path.hip", "paper_1006_3340_amd/csrc/mlp.hpp",
@@ -65,8 +65,15 @@ def source_hash(sources) -> str:
     return h.hexdigest()[:16]
 
 
+def fp32_bucket(n_rates: int) -> int:
+    """Register slots of the FP32 single-structure path kernel that runs N rates."""
+    return next(b for b in (8, 16, 20, 24, 32, 40) if n_rates <= b)
+
+
 def kernel_hash() -> str:
     return source_hash(KERNEL_SOURCES)
+
+
 Q = 64
 METRIC = "path-steps/s: full Euler vs Picard vs MLP drift, at <=1e-4 rel caplet error"
 
@@ -643,7 +650,7 @@ def main(argv=None) -> int:
         "config": {"workload": ts.name, "n_rates": ts.n_rates, "delta": 0.5,
                    "steps_per_period": ts.steps_per_period, "n_paths": n,
                    "n_strikes": ts.n_strikes, "driver": "NIG(18,-4,1)", "schemes": schemes},
-        "roofline": {"bound": "alu", "kernel": f"path_kernel<float,24,{dom}>",
+        "roofline": {"bound": "alu", "kernel": f"path_kernel<float,{fp32_bucket(ts.n_rates)},{dom}>",
                      "achieved": fl_dom / (ms_dom / 1e3) / 1e12, "peak": PEAK_FP32 / 1e12,
                      "unit": "TFLOP/s", "frac": fl_dom / (ms_dom / 1e3) / PEAK_FP32,
                      "traffic": TRAFFIC_BYTES.get(kernel_hash(), {}).get(dom),

@@ -121,7 +121,7 @@ void fill_plan_header(lll_plan &p, const lll_term_structure *ts, int precision, 
     p.K = p.N * p.s;
     p.driver = ts->driver;
     p.precision = precision;
-    p.nmax = nmax > 0 ? nmax : bucket_for(p.N);
+    p.nmax = nmax > 0 ? nmax : bucket_for(p.N, precision == LLL_FP32);
     p.off = p.nmax - p.N;
     p.struct_id = ts->struct_id;
     p.product = ts->product;
@@ -682,7 +682,9 @@ int lll_batch_create(const lll_term_structure *ts, int n_ts, int64_t max_paths_e
     b->max_paths_each = max_paths_each;
     for (int i = 0; i < n_ts; ++i) {
         lll_plan *p = nullptr;
-        int rc = create_plan(&ts[i], LLL_FP32, max_paths_each, 0, &p);
+        // the persistent kernels come in the 8/16/24/32/40-slot buckets
+        int rc = create_plan(&ts[i], LLL_FP32, max_paths_each,
+                             lll::bucket_for(ts[i].n_rates, false), &p);
         if (rc != LLL_OK) {
             lll_batch_destroy(b);
             return rc;

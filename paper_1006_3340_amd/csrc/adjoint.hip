@@ -10,6 +10,7 @@ namespace adj {
 
 extern template hipError_t launch_adjoint_bucket<8>(const PathArgs<float> &, const AdjArgs &, hipStream_t);
 extern template hipError_t launch_adjoint_bucket<16>(const PathArgs<float> &, const AdjArgs &, hipStream_t);
+extern template hipError_t launch_adjoint_bucket<20>(const PathArgs<float> &, const AdjArgs &, hipStream_t);
 extern template hipError_t launch_adjoint_bucket<24>(const PathArgs<float> &, const AdjArgs &, hipStream_t);
 extern template hipError_t launch_adjoint_bucket<32>(const PathArgs<float> &, const AdjArgs &, hipStream_t);
 extern template hipError_t launch_adjoint_bucket<40>(const PathArgs<float> &, const AdjArgs &, hipStream_t);
@@ -18,6 +19,7 @@ extern template hipError_t launch_adjoint_bucket<40>(const PathArgs<float> &, co
                                                      const VjpArgs &, hipStream_t);
 LLL_VJP_EXTERN(8)
 LLL_VJP_EXTERN(16)
+LLL_VJP_EXTERN(20)
 LLL_VJP_EXTERN(24)
 LLL_VJP_EXTERN(32)
 LLL_VJP_EXTERN(40)
@@ -255,6 +257,7 @@ hipError_t launch_greeks_vjp(const lll_plan &p, int64_t n_paths, uint64_t seed,
     switch (p.nmax) {
         case 8: e = launch_vjp_bucket<8>(a, g, v, st); break;
         case 16: e = launch_vjp_bucket<16>(a, g, v, st); break;
+        case 20: e = launch_vjp_bucket<20>(a, g, v, st); break;
         case 24: e = launch_vjp_bucket<24>(a, g, v, st); break;
         case 32: e = launch_vjp_bucket<32>(a, g, v, st); break;
         case 40: e = launch_vjp_bucket<40>(a, g, v, st); break;
@@ -282,6 +285,7 @@ hipError_t launch_greeks(const lll_plan &p, int64_t n_paths, uint64_t seed, hipS
     switch (p.nmax) {
         case 8: e = launch_adjoint_bucket<8>(a, g, st); break;
         case 16: e = launch_adjoint_bucket<16>(a, g, st); break;
+        case 20: e = launch_adjoint_bucket<20>(a, g, st); break;
         case 24: e = launch_adjoint_bucket<24>(a, g, st); break;
         case 32: e = launch_adjoint_bucket<32>(a, g, st); break;
         case 40: e = launch_adjoint_bucket<40>(a, g, st); break;

@@ -554,6 +554,7 @@ hipError_t launch_exact_t(const lll_plan &p, int64_t n_paths, int64_t path_offse
             switch (p.nmax) {
                 case 8: e = launch_payoff_n<Real, 8>(a, xs, m, st); break;
                 case 16: e = launch_payoff_n<Real, 16>(a, xs, m, st); break;
+                case 20: e = launch_payoff_n<Real, 20>(a, xs, m, st); break;
                 case 24: e = launch_payoff_n<Real, 24>(a, xs, m, st); break;
                 default: e = hipErrorInvalidValue;
             }

@@ -14,10 +14,12 @@ namespace lll {
 constexpr int kWaveSize = 64;  // CDNA wavefront
 constexpr int kQSize = 64;     // quadrature nodes
 
-// Smallest register bucket holding N rates.  Rates live in register slots
-// off .. off + N - 1 with off = nmax - N, so that the live rates of every
-// period are a suffix of the bucket and all slot indices are compile-time.
-int bucket_for(int n_rates);
+// Smallest register bucket holding N rates: 8, 16, 20 (with slots20: FP32
+// single-structure plans), 24, 32, 40, and 64 for the tables of the
+// maturity-parallel scheme.  Rates live in register slots off .. off + N - 1
+// with off = nmax - N, so that the live rates of every period are a suffix of
+// the bucket and all slot indices are compile-time.
+int bucket_for(int n_rates, bool slots20);
 
 struct DeviceTables {
     // FP64 inputs (device)

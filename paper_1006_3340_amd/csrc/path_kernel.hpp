@@ -489,7 +489,7 @@ __device__ __forceinline__ void simulate_lds(const PathArgs<Real> &a, int64_t gi
 // in LDS (measured: N = 20 FULL 22.7 -> 21.2 ms, N = 40 FULL 50.0 -> 42.7 ms,
 // N = 40 PICARD 70.6 -> 58.0 ms at 2^20 paths).
 template <typename Real, int NMAX, int SCHEME>
-constexpr bool kStateInLds = sizeof(Real) == 4 && NMAX >= 24 && SCHEME != kFrozen;
+constexpr bool kStateInLds = sizeof(Real) == 4 && NMAX >= 20 && SCHEME != kFrozen;
 
 // Simulates path `gid` (0-based within the structure; lanes past n_paths run
 // but contribute nothing) through all periods, writing the wave's payoff sums.
@@ -686,8 +686,8 @@ hipError_t launch_drift_bucket(const lll_plan &p, int k, const double *L, int64_
                                                             hipStream_t);
 
 #define LLL_BUCKET_LIST(X)                                                                        \
-    X(float, 8) X(float, 16) X(float, 24) X(float, 32) X(float, 40) X(double, 8) X(double, 16)   \
-        X(double, 24)
+    X(float, 8) X(float, 16) X(float, 20) X(float, 24) X(float, 32) X(float, 40) X(double, 8)    \
+        X(double, 16) X(double, 24)
 
 #define LLL_BUCKET_EXTERN(REAL, NMAX) LLL_BUCKET_DECL(extern, REAL, NMAX)
 #ifndef LLL_BUCKET_TU

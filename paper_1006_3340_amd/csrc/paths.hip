@@ -140,9 +140,10 @@ __global__ void __launch_bounds__(64) finalize_kernel(const double *__restrict__
 
 }  // namespace
 
-int bucket_for(int n_rates) {
+int bucket_for(int n_rates, bool slots20) {
     if (n_rates <= 8) return 8;
     if (n_rates <= 16) return 16;
+    if (slots20 && n_rates <= 20) return 20;
     if (n_rates <= 24) return 24;
     if (n_rates <= 32) return 32;
     if (n_rates <= 40) return 40;
@@ -163,6 +164,7 @@ hipError_t launch_paths(const lll_plan &p, int scheme, int64_t n_paths, int64_t 
     switch (p.nmax) {
         case 8: return launch_bucket<float, 8>(p, scheme, n_paths, path_offset, seed, path_fix, st);
         case 16: return launch_bucket<float, 16>(p, scheme, n_paths, path_offset, seed, path_fix, st);
+        case 20: return launch_bucket<float, 20>(p, scheme, n_paths, path_offset, seed, path_fix, st);
         case 24: return launch_bucket<float, 24>(p, scheme, n_paths, path_offset, seed, path_fix, st);
         case 32: return launch_bucket<float, 32>(p, scheme, n_paths, path_offset, seed, path_fix, st);
         case 40: return launch_bucket<float, 40>(p, scheme, n_paths, path_offset, seed, path_fix, st);
@@ -184,6 +186,7 @@ hipError_t launch_drift(const lll_plan &p, int k, const double *L_dev, int64_t n
     switch (p.nmax) {
         case 8: return launch_drift_bucket<float, 8>(p, k, L_dev, n, b_dev, st);
         case 16: return launch_drift_bucket<float, 16>(p, k, L_dev, n, b_dev, st);
+        case 20: return launch_drift_bucket<float, 20>(p, k, L_dev, n, b_dev, st);
         case 24: return launch_drift_bucket<float, 24>(p, k, L_dev, n, b_dev, st);
         case 32: return launch_drift_bucket<float, 32>(p, k, L_dev, n, b_dev, st);
         case 40: return launch_drift_bucket<float, 40>(p, k, L_dev, n, b_dev, st);

@@ -555,6 +555,7 @@ hipError_t launch_picard_mp(const lll_plan &p, int64_t n_paths, int64_t path_off
         switch (p.nmax) {
             case 8: launch_mp_payoff<8>(pa, a.z, pays, first, n_chunk, zs, st); break;
             case 16: launch_mp_payoff<16>(pa, a.z, pays, first, n_chunk, zs, st); break;
+            case 20: launch_mp_payoff<20>(pa, a.z, pays, first, n_chunk, zs, st); break;
             case 24: launch_mp_payoff<24>(pa, a.z, pays, first, n_chunk, zs, st); break;
             case 32: launch_mp_payoff<32>(pa, a.z, pays, first, n_chunk, zs, st); break;
             case 40: launch_mp_payoff<40>(pa, a.z, pays, first, n_chunk, zs, st); break;

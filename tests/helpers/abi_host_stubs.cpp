@@ -9,7 +9,7 @@
 #include "lll_internal.hpp"
 
 namespace lll {
-int bucket_for(int n) { return n <= 8 ? 8 : n <= 16 ? 16 : n <= 24 ? 24 : n <= 32 ? 32 : n <= 40 ? 40 : 64; }
+int bucket_for(int n, bool slots20) { return n <= 8 ? 8 : n <= 16 ? 16 : (slots20 && n <= 20) ? 20 : n <= 24 ? 24 : n <= 32 ? 32 : n <= 40 ? 40 : 64; }
 hipError_t greeks_alloc(lll_plan &) { return hipErrorNotSupported; }
 void greeks_free(lll_plan &) {}
 void mlp_plan_free(lll_plan &) {}
