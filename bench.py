@@ -44,11 +44,11 @@ MLP_SOURCES = ["paper_1006_3340_amd/csrc/mlp_path.hip", "paper_1006_3340_amd/csr
 # rocprofv3 --pmc figures of the surrogate pricing kernel at 2^20 paths
 # (profiles/mlp_kernels_mlp_n40_mfma_counters.md), by source hash: a changed
 # kernel reports none
-MLP_COUNTERS = {"355912e492cb5187": {
+MLP_COUNTERS = {"abe10e13b468af42": {
     "source": "profiles/mlp_kernels_mlp_n40_mfma_counters.md",
-    "mlp_path_kernel_ms": 524.53, "clock_ghz": 2.38,
-    "counted_mfma_flop": 2.178e+14, "counted_mfma_tflops": 415.1,
-    "mfma_busy": 0.166, "valu_busy": 0.851, "trans_share_of_valu": 0.222}}
+    "mlp_path_kernel_ms": 524.01, "clock_ghz": 2.37,
+    "counted_mfma_flop": 2.178e+14, "counted_mfma_tflops": 415.6,
+    "mfma_busy": 0.167, "valu_busy": 0.853, "trans_share_of_valu": 0.222}}
 
 
 def source_hash(sources) -> str:
