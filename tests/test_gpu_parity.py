@@ -412,16 +412,16 @@ def _swaption_greeks_structure(N=8):
     return workloads.coterminal_swaptions(_greeks_structure(N), [1.0])
 
 
-def _oracle_fd(oracle_mod, N, n, h, product=0):
+def _oracle_fd(oracle_mod, N, n, h, product=0, columns=None):
     """Central differences of the FP64 oracle's FULL prices (caplets, or
     co-terminal swaptions for product 1) under common random numbers: bumps of
     L(0,T_l) and of the vol level v_l (B(0,T_1) and the absolute strikes
-    held)."""
+    held), for the input columns l given (all by default; the others stay 0)."""
     L0 = 0.03 + 0.001 * np.arange(1, N + 1)
     lv = np.full(N, 0.12)
     K = (_swaption_greeks_structure(N) if product else _greeks_structure(N)).strikes
     JL = np.zeros((N, N)); JV = np.zeros((N, N))
-    for l in range(N):
+    for l in (range(N) if columns is None else columns):
         for J, bump in ((JL, "L"), (JV, "v")):
             prices = []
             for sgn in (+1, -1):
@@ -444,6 +444,31 @@ def test_greeks_match_oracle_finite_differences(gpu_lib, oracle_mod, h, rtol):
     for got, ref in ((g["dP_dL0"], JL), (g["dP_dvol"], JV)):
         scale = np.max(np.abs(ref), axis=1, keepdims=True)
         assert np.all(np.abs(got - ref) <= rtol * np.abs(ref) + rtol * 1e-2 * scale), (got, ref)
+    ref_price = oracle_mod.Oracle(ts, seed=1).price(FULL, n)["price"][:, 0]
+    assert np.allclose(g["price"], ref_price, rtol=1e-4)
+
+
+def test_greeks_20_slot_bucket_match_oracle_finite_differences(gpu_lib, oracle_mod):
+    """N = 20 runs the 20-slot adjoint kernels (FP32 plans of 17..20 rates):
+    Greeks and the single-sweep vector-Jacobian product against the oracle's
+    common-random-number central differences for the columns l = 0, 10, 19
+    (h = 1e-6, the caplet bar of 2e-3)."""
+    N, n, h, rtol, cols = 20, 2000, 1e-6, 2e-3, (0, 10, 19)
+    ts = _greeks_structure(N)
+    w = np.linspace(-1.0, 1.5, N)
+    with gpu_lib.Plan(ts, precision=0, max_paths=n) as plan:
+        plan.greeks(n, seed=1)
+        g = plan.greeks_results()
+        plan.greeks_vjp(n, w, seed=1)
+        v = plan.greeks_vjp_results()
+    JL, JV = _oracle_fd(oracle_mod, N, n, h, columns=cols)
+    for got, ref, vj in ((g["dP_dL0"], JL, v["vjp_L0"]), (g["dP_dvol"], JV, v["vjp_vol"])):
+        for l in cols:
+            scale = np.max(np.abs(ref[:, l]))
+            err = np.abs(got[:, l] - ref[:, l])
+            assert np.all(err <= rtol * np.abs(ref[:, l]) + rtol * 1e-2 * scale), (l, got[:, l], ref[:, l])
+            bound = rtol * (np.abs(w) @ np.abs(ref[:, l]) + 1e-2 * scale * np.abs(w).sum())
+            assert abs(vj[l] - w @ ref[:, l]) <= bound, (l, vj[l], w @ ref[:, l])
     ref_price = oracle_mod.Oracle(ts, seed=1).price(FULL, n)["price"][:, 0]
     assert np.allclose(g["price"], ref_price, rtol=1e-4)
 
