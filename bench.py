@@ -44,7 +44,7 @@ MLP_SOURCES = ["paper_1006_3340_amd/csrc/mlp_path.hip", "paper_1006_3340_amd/csr
 # rocprofv3 --pmc figures of the surrogate pricing kernel at 2^20 paths
 # (profiles/mlp_kernels_mlp_n40_mfma_counters.md), by source hash: a changed
 # kernel reports none
-MLP_COUNTERS = {"abe10e13b468af42": {
+MLP_COUNTERS = {"653b1a0fa29f8bbc": {
     "source": "profiles/mlp_kernels_mlp_n40_mfma_counters.md",
     "mlp_path_kernel_ms": 524.01, "clock_ghz": 2.37,
     "counted_mfma_flop": 2.178e+14, "counted_mfma_tflops": 415.6,

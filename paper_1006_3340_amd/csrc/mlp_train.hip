@@ -434,8 +434,15 @@ __global__ void __launch_bounds__(kTrainBlock) tile_kernel(TileArgs t) {
     }
 }
 
-// Sum of the block gradients in block order; with lr > 0 an Adam step of the
-// FP32 master weights (and a refresh of the BF16 copy).
+// Sum of the tile gradients and, with lr > 0, an Adam step of the FP32 master
+// weights (and a refresh of the BF16 copy).  A block takes 32 parameters; each
+// parameter's tiles are split into 8 contiguous slices summed by 8 threads at
+// once (coalesced rows of 32 parameters), then the slices in slice order: a
+// fixed summation order, the same in every call.  Block 0 sums the tile losses
+// the same way.
+constexpr int kSlices = 8;
+constexpr int kParamsPerBlock = 256 / kSlices;
+
 __global__ void __launch_bounds__(256) reduce_adam_kernel(const float *__restrict__ gpart,
                                                           int tiles, const float *__restrict__ lpart,
                                                           float *__restrict__ loss_out,
@@ -444,15 +451,31 @@ __global__ void __launch_bounds__(256) reduce_adam_kernel(const float *__restric
                                                           float *__restrict__ adam,
                                                           float *__restrict__ grad_out, float lr,
                                                           float bc1, float bc2) {
-    const int p = blockIdx.x * 256 + threadIdx.x;
-    if (p == 0 && loss_out) {
-        float s = 0.0f;
-        for (int i = 0; i < tiles; ++i) s += lpart[i];
-        *loss_out = s;
+    __shared__ float part[kSlices][kParamsPerBlock];
+    __shared__ float lsum[kSlices];
+    const int pl = threadIdx.x % kParamsPerBlock, sl = threadIdx.x / kParamsPerBlock;
+    const int p = blockIdx.x * kParamsPerBlock + pl;
+    const int per = (tiles + kSlices - 1) / kSlices;
+    const int t0 = sl * per, t1 = min(tiles, t0 + per);
+    float s = 0.0f;
+    if (p < kParams)
+        for (int i = t0; i < t1; ++i) s += gpart[static_cast<int64_t>(i) * kParams + p];
+    part[sl][pl] = s;
+    if (blockIdx.x == 0 && loss_out && pl == 0) {
+        float l = 0.0f;
+        for (int i = t0; i < t1; ++i) l += lpart[i];
+        lsum[sl] = l;
     }
-    if (p >= kParams) return;
-    float gsum = 0.0f;
-    for (int i = 0; i < tiles; ++i) gsum += gpart[static_cast<int64_t>(i) * kParams + p];
+    __syncthreads();
+    if (blockIdx.x == 0 && loss_out && threadIdx.x == 0) {
+        float l = lsum[0];
+        for (int k = 1; k < kSlices; ++k) l += lsum[k];
+        *loss_out = l;
+    }
+    if (sl != 0 || p >= kParams) return;
+    float gsum = part[0][pl];
+#pragma unroll
+    for (int k = 1; k < kSlices; ++k) gsum += part[k][pl];
     if (grad_out) grad_out[p] = gsum;
     if (lr > 0.0f) {
         const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
@@ -526,7 +549,8 @@ hipError_t launch_tiles(const __bf16 *feat, const float *target, const int *idx,
     hipLaunchKernelGGL(tile_kernel, dim3(tiles), dim3(kTrainBlock), 0, st, t);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !gpart) return e;
-    hipLaunchKernelGGL(reduce_adam_kernel, dim3((kParams + 255) / 256), dim3(256), 0, st, gpart,
+    hipLaunchKernelGGL(reduce_adam_kernel, dim3((kParams + kParamsPerBlock - 1) / kParamsPerBlock),
+                       dim3(256), 0, st, gpart,
                        tiles, lpart, loss_out, wts_mut, wbf_mut, adam, grad_out, lr, bc1, bc2);
     return hipGetLastError();
 }
