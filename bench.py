@@ -232,12 +232,12 @@ PEAK_BF16 = 2.5e15     # MI355X dense BF16 matrix cores, FLOP/s
 def mlp_flops_per_rate_step(n_later: int) -> dict:
     """Algorithmic flops of the surrogate coupling of one rate with n_later later
     rates (FMA = 2): on the matrix cores the first layer over the later rates'
-    states (2 x 64 x n_later; the time and one-hot inputs are a bias table) and
-    the two 64x64 hidden layers; on the vector ALU the first-order expansion
-    (2 per later rate), three 64-wide GELU layers (8 per unit) and the output
-    dot (128)."""
-    return {"mfma": 2 * 64 * n_later + 2 * 2 * 64 * 64,
-            "valu": 2 * n_later + 3 * 8 * 64 + 128}
+    states (2 x 64 x n_later; the time and one-hot inputs are a bias table), the
+    two 64x64 hidden layers and the output dot (128); on the vector ALU the
+    first-order expansion (2 per later rate) and three 64-wide GELU layers (8
+    per unit)."""
+    return {"mfma": 2 * 64 * n_later + 2 * 2 * 64 * 64 + 128,
+            "valu": 2 * n_later + 3 * 8 * 64}
 
 
 def bench_mlp(lll, stream, n: int = 1 << 20, train_steps: int = 3000) -> dict:
