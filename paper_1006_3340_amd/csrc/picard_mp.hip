@@ -115,87 +115,103 @@ __global__ void __launch_bounds__(kBlock) mp_increments_kernel(MpArgs a) {
     a.dh[e] = static_cast<float>(increment(w, cst, a.beta, false, nullptr));
 }
 
-// Vol, -kappa dt and frozen drift of slot j for steps kb .. kb+3 (clamped to
-// the last step).
-__device__ __forceinline__ void load_tables4(const MpArgs &a, int kb, int j, float (&lam)[4],
-                                             float (&d0)[4], float (&frz)[4]) {
+// Table values and driver increments of steps kb .. kb+3 (clamped to the last
+// step): vol, cumulant term and frozen drift of slot j (byte offsets into the
+// K x nmax tables stay below 2^32: K <= 2^24, nmax <= 64), and the 4 paths'
+// increments (one 16-byte load, the same address on every lane).
+struct Steps4 {
+    float lam[4], d0[4], frz[4];
+    float4 dh[4];
+};
+__device__ __forceinline__ void load_steps4(const MpArgs &a, const float4 *dh_g, int kb,
+                                            unsigned j, Steps4 &t) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-        const size_t t = (size_t)min(kb + u, a.K - 1) * a.nmax + j;
-        lam[u] = a.lam[t];
-        d0[u] = a.drift0[t];
-        frz[u] = a.frozen[t];
+        const int k = min(kb + u, a.K - 1);
+        const unsigned b = ((unsigned)k * (unsigned)a.nmax + j) * 4u;
+        t.lam[u] = *(cptr<float>)((cptr<char>)a.lam + b);
+        t.d0[u] = *(cptr<float>)((cptr<char>)a.drift0 + b);
+        t.frz[u] = *(cptr<float>)((cptr<char>)a.frozen + b);
+        t.dh[u] = dh_g[k];
     }
 }
 
+// Predictor state of one group: X1 and the running first sums A of the 4
+// paths, the period m of the next step and the step's place kk in it, and e,
+// the ell^ entry of that step's first live rate (ell_entry(k, s, N)).
+struct Predictor {
+    float X1[kGroup], A[kGroup];
+    int m, kk;
+    size_t e;
+};
+
+// Steps kb .. kb+3 (those below K) of one group: ell^ at the predictor, then
+// the predictor and the first sums advanced; Z's first sums stored at each
+// period's last step.
+__device__ __forceinline__ void prologue_steps4(const MpArgs &a, const Steps4 &t, int kb, int lane,
+                                                int r, float ci, float4 *ell_g, float4 *z_g,
+                                                Predictor &q) {
+    const int N = a.N;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        if (kb + u < a.K) {
+            const bool live = lane >= q.m && lane < N;
+            if (live)
+                ell_g[q.e + (r - q.m)] =
+                    make_float4(detail::ell_of(q.X1[0], ci), detail::ell_of(q.X1[1], ci),
+                                detail::ell_of(q.X1[2], ci), detail::ell_of(q.X1[3], ci));
+            const float d[kGroup] = {t.dh[u].x, t.dh[u].y, t.dh[u].z, t.dh[u].w};
+#pragma unroll
+            for (int p = 0; p < kGroup; ++p) {
+                q.A[p] += fmaf(t.lam[u], d[p], t.d0[u]);
+                q.X1[p] += fmaf(t.lam[u], d[p], t.frz[u]);
+            }
+            q.e += N - q.m;
+            if (++q.kk == a.s) {  // last step of period m
+                if (live) z_g[(size_t)q.m * N + r] = make_float4(q.A[0], q.A[1], q.A[2], q.A[3]);
+#pragma unroll
+                for (int p = 0; p < kGroup; ++p) q.A[p] = 0.0f;
+                q.kk = 0;
+                ++q.m;
+            }
+        }
+    }
+}
+
+// One wavefront per group of 4 paths, lane = rate.  The steps run in order
+// with the period and the step within it carried along, so that ell^'s entry
+// and the period's live lanes advance by additions; the loads of the next 4
+// steps are issued while the current 4 steps compute (a step's own loads
+// would otherwise wait a full L2 round trip), into two register sets used in
+// turn.  A fixed rate's vol, cumulant and frozen drift are 0, so its updates
+// add nothing.  Stores are 16 B per lane, contiguous over the live rates.
 __global__ void __launch_bounds__(kBlock) mp_prologue_kernel(MpArgs a) {
-    __shared__ float sdh[kWavesPerBlock][kGroup][kWave];
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = threadIdx.x % kWave;
     const int g = blockIdx.x * kWavesPerBlock + wv;
     if (g >= a.G) return;  // whole wavefront
-    float(*dh)[kWave] = sdh[wv];
     const int N = a.N, K = a.K, s = a.s;
     // rate of this lane (N <= 64); lanes past the last rate repeat it and
-    // store the same values to the same places
+    // store nothing
     const int r = lane < N ? lane : N - 1;
-    const int j = a.off + r;
+    const unsigned j = static_cast<unsigned>(a.off + r);
     const float ci = a.cinv[j];
-    float X1[kGroup], A[kGroup];
-#pragma unroll
-    for (int p = 0; p < kGroup; ++p) X1[p] = A[p] = 0.0f;
     const float4 *dh_g = reinterpret_cast<const float4 *>(a.dh) + (size_t)g * K;
     float4 *ell_g = reinterpret_cast<float4 *>(a.ellhat) + (size_t)g * ell_entries(s, N);
     float4 *z_g = reinterpret_cast<float4 *>(a.z) + (size_t)g * z_entries(N);
-    for (int k0 = 0; k0 < K; k0 += kWave) {
-        const int kd = k0 + lane;
-        if (kd < K) {
-            const float4 d = dh_g[kd];
-            dh[0][lane] = d.x;
-            dh[1][lane] = d.y;
-            dh[2][lane] = d.z;
-            dh[3][lane] = d.w;
-        }
-        wave_sync();
-        const int kn = min(kWave, K - k0);
-        // The table values of the next 4 steps are loaded while the current 4
-        // steps compute (a step's own loads would otherwise wait a full L2
-        // round trip).  They do not depend on the rate being live (a fixed
-        // rate's vol, cumulant and frozen drift are 0, so its updates add
-        // nothing).  Stores are 16 B per lane, contiguous over the live rates.
-        float cl[4], cd[4], cf[4], nl[4], nd[4], nf[4];
-        load_tables4(a, k0, j, cl, cd, cf);
-        for (int kk = 0; kk < kn; kk += 4) {
-            load_tables4(a, k0 + kk + 4, j, nl, nd, nf);
+    Predictor q;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                if (kk + u < kn) {
-                    const int k = k0 + kk + u;
-                    const int m = k / s;
-                    const bool live = lane >= m && lane < N;
-                    if (live)
-                        ell_g[ell_entry(k, s, N) + (r - m)] =
-                            make_float4(detail::ell_of(X1[0], ci), detail::ell_of(X1[1], ci),
-                                        detail::ell_of(X1[2], ci), detail::ell_of(X1[3], ci));
-                    const bool first = k == m * s;
-#pragma unroll
-                    for (int p = 0; p < kGroup; ++p) {
-                        const float d = dh[p][kk + u];
-                        A[p] = (first ? 0.0f : A[p]) + fmaf(cl[u], d, cd[u]);
-                        X1[p] += fmaf(cl[u], d, cf[u]);
-                    }
-                    if (k + 1 == (m + 1) * s && live)
-                        z_g[(size_t)m * N + r] = make_float4(A[0], A[1], A[2], A[3]);
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                cl[u] = nl[u];
-                cd[u] = nd[u];
-                cf[u] = nf[u];
-            }
-        }
-        wave_sync();
+    for (int p = 0; p < kGroup; ++p) q.X1[p] = q.A[p] = 0.0f;
+    q.m = q.kk = 0;
+    q.e = 0;
+    Steps4 t0, t1;
+    load_steps4(a, dh_g, 0, j, t0);
+    for (int k0 = 0; k0 < K; k0 += 8) {
+        load_steps4(a, dh_g, k0 + 4, j, t1);
+        prologue_steps4(a, t0, k0, lane, r, ci, ell_g, z_g, q);
+        if (k0 + 4 >= K) break;
+        load_steps4(a, dh_g, k0 + 8, j, t0);
+        prologue_steps4(a, t1, k0 + 4, lane, r, ci, ell_g, z_g, q);
     }
 }
 
