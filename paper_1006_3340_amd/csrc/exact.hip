@@ -472,12 +472,19 @@ exact_period_kernel(PathArgs<Real> a, cptr<Real> kex,
 }
 
 // Payoffs at the end of period m from the states in HBM: one path per lane
-// and the path kernels' payoff code (per-wavefront partials).
+// and the path kernels' payoff code (per-wavefront partials).  The first live
+// slot is j0 = off + m >= NMAX - LLL_N_MAX_EXACT (N <= LLL_N_MAX_EXACT), so
+// only the slots from kJ0Min on get a copy of the payoff code.
+template <int NMAX>
+constexpr int kJ0Min = NMAX > LLL_N_MAX_EXACT ? NMAX - LLL_N_MAX_EXACT : 0;
+
 template <typename Real, int NMAX, int PRODUCT, int... Js>
 __device__ __forceinline__ void exact_payoff_dispatch(std::integer_sequence<int, Js...>, int j0,
                                                       const PathArgs<Real> &a, int m, int64_t gid,
                                                       bool active, const Real (&X)[NMAX]) {
-    (void)((j0 == Js ? (detail::payoff<Real, NMAX, Js, PRODUCT>(a, m, gid, active, X), 0) : 0) +
+    (void)((j0 == kJ0Min<NMAX> + Js
+                ? (detail::payoff<Real, NMAX, kJ0Min<NMAX> + Js, PRODUCT>(a, m, gid, active, X), 0)
+                : 0) +
            ...);
 }
 
@@ -493,8 +500,8 @@ __global__ void __launch_bounds__(kBlock) exact_payoff_kernel(PathArgs<Real> a,
 #pragma unroll
     for (int j = 0; j < NMAX; ++j)
         X[j] = (j >= j0 && active) ? xs[static_cast<int64_t>(j - a.off) * a.n_paths + gid] : Real(0);
-    exact_payoff_dispatch<Real, NMAX, PRODUCT>(std::make_integer_sequence<int, NMAX>{}, j0, a, m,
-                                               gid, active, X);
+    exact_payoff_dispatch<Real, NMAX, PRODUCT>(
+        std::make_integer_sequence<int, NMAX - kJ0Min<NMAX>>{}, j0, a, m, gid, active, X);
 }
 
 template <typename Real>
