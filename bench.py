@@ -30,10 +30,9 @@ PEAK_FP32 = 157.3e12   # MI355X vector FP32, FLOP/s
 
 # HBM bytes per path-kernel launch from rocprofv3 --pmc FETCH_SIZE and
 # WRITE_SIZE runs of this benchmark, each scaled by the same counter's reading
-# for a 1 GiB device copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0), keyed by the
-# hash of the kernel sources they were taken on; any other hash reports null.
-# calibrated HBM bytes per launch (profiles/path_kernel_gpu_n20_counters.md), by
-# source hash of the path kernels: a changed kernel reports none
+# for a 1 GiB device copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0;
+# profiles/path_kernel_gpu_n20_counters.md), keyed by the hash of the kernel
+# sources they were taken on; any other hash reports null.
 TRAFFIC_BYTES = {"92e05cbf6a5b5222": {"full": 146993080, "picard": 166064311}}
 KERNEL_SOURCES = ["paper_1006_3340_amd/csrc/path_kernel.hpp",
                   "paper_1006_3340_amd/csrc/lll_device.hpp"]
