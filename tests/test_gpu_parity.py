@@ -633,3 +633,29 @@ def test_swaption_identities_on_gpu(gpu_lib):
                 p.execute(FULL, 4096, seed=2)
                 assert np.allclose(bt.results(i)["price"], p.results()["price"], rtol=1e-6,
                                    atol=1e-300)
+
+
+@pytest.mark.parametrize("precision,product", [(0, "caplets"), (1, "caplets"), (0, "swaptions"),
+                                               (1, "swaptions")])
+def test_eight_strikes_the_most_a_plan_takes(gpu_lib, oracle_mod, precision, product):
+    """LLL_S_MAX = 8 strikes per caplet (26 partial sums per rate and
+    wavefront), FULL and PICARD, FP32 and FP64 kernels, caplets and swaptions,
+    against the oracle on the same streams."""
+    mults = list(np.linspace(0.65, 1.35, 8))
+    ts = workloads.make_structure(12, 0.5, 0.03 + 0.001 * np.arange(12), 4,
+                                  workloads.exp_decay_vol(), mults)
+    if product == "swaptions":
+        ts = workloads.coterminal_swaptions(ts, mults)
+    assert ts.n_strikes == 8
+    n = 1500
+    o = _oracle(oracle_mod, ts, seed=3)
+    with gpu_lib.Plan(ts, precision=precision, max_paths=n) as plan:
+        for scheme in (FULL, PICARD):
+            ref = o.price(scheme, n)
+            plan.execute(scheme, n, seed=3)
+            got = plan.results()
+            if precision == 1:
+                assert np.array_equal(got["n_itm"], ref["n_itm"])
+                assert np.allclose(got["price"], ref["price"], rtol=1e-10, atol=1e-300)
+            else:
+                _check_prices(got, ref, ts, 1e-4)
